@@ -1,0 +1,171 @@
+"""Seeded synthetic baseband for the hybrid beamformer.
+
+This module only simulates what the F-engine would deliver: Gaussian noise
+plus monochromatic point sources seen by the CHIME array, quantised to 4+4-bit
+offset-binary complex samples.  It holds no beamforming arithmetic and is
+shared by the oracle tests and the GPU tests/benchmark as their common input.
+
+Array model (paper Sec. 1): four cylinders, each with 256 dual-polarisation
+feeds at 0.3048 m N-S spacing; cylinders are 20 m wide and sit side by side,
+so cylinder c is at x_c = (c - 1.5) * 20 m (east positive) and feed n at
+y_n = n * 0.3048 m (north positive).  A source in direction (u, v) =
+(sin phi, cos phi * sin theta) -- phi the E-W offset, theta the N-S zenith
+angle -- reaches input (c, n, p) with phase exp(+2 pi i f (x_c u + y_n v)/c0).
+
+Byte layout: ``raw[frame][chan][t][i]`` with t < 384 samples of 2.56 us and
+i = (cyl * 256 + feed) * 2 + pol; byte = ((re + 8) << 4) | (im + 8).
+Quantisation: sigma applies per real component, values are rounded half to
+even and clipped to [-7, 7]; sources are added before rounding.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+C0 = 299_792_458.0
+FEED_SPACING_M = 0.3048
+CYL_SPACING_M = 20.0
+N_CYL, N_FEED, N_POL = 4, 256, 2
+N_INPUTS = N_CYL * N_FEED * N_POL
+N_TIME = 384                 # samples per 0.983 ms frame
+SAMPLE_DT = 2.56e-6          # s
+CHAN_BW_HZ = 390_625.0
+F_BOTTOM_HZ = 400e6
+SUBCHAN_HZ = CHAN_BW_HZ / 16.0
+SIGMA = 2.5
+
+
+def chan_freq_hz(c_idx) -> np.ndarray:
+    """Centre frequency of F-engine channel c_idx (1024 channels, 400-800 MHz)."""
+    return F_BOTTOM_HZ + np.asarray(c_idx, dtype=np.float64) * CHAN_BW_HZ
+
+
+def encode(re: np.ndarray, im: np.ndarray) -> np.ndarray:
+    """Integers in [-8, 7] -> offset-binary 4+4-bit bytes (high nibble real)."""
+    return (((re.astype(np.int16) + 8) << 4) | (im.astype(np.int16) + 8)).astype(np.uint8)
+
+
+def input_positions():
+    """(x, y) in metres of each of the 2048 inputs, in input order."""
+    i = np.arange(N_INPUTS)
+    cyl = i // (N_FEED * N_POL)
+    feed = (i // N_POL) % N_FEED
+    x = (cyl - (N_CYL - 1) / 2.0) * CYL_SPACING_M
+    y = feed * FEED_SPACING_M
+    return x, y
+
+
+@dataclass
+class Source:
+    """Monochromatic point source.  tone_hz is the offset from the channel centre."""
+    sin_theta: float         # N-S zenith angle sine
+    phi_deg: float           # E-W offset
+    amp: float               # amplitude per real+imag sample
+    tone_hz: float = 0.0
+    phase: float = 0.0
+
+
+def _spatial(freq_hz: float, sources) -> np.ndarray:
+    x, y = input_positions()
+    rows = []
+    for s in sources:
+        phi = np.deg2rad(s.phi_deg)
+        u = np.sin(phi)
+        v = np.cos(phi) * s.sin_theta
+        rows.append(np.exp(2j * np.pi * freq_hz * (x * u + y * v) / C0))
+    return np.asarray(rows, dtype=np.complex128).reshape(len(sources), N_INPUTS)
+
+
+def _temporal(t_abs: np.ndarray, sources) -> np.ndarray:
+    cols = [s.amp * np.exp(1j * (2 * np.pi * s.tone_hz * t_abs * SAMPLE_DT + s.phase))
+            for s in sources]
+    return np.asarray(cols, dtype=np.complex128).reshape(len(sources), t_abs.size).T
+
+
+def channel_frames(rng: np.random.Generator, freq_hz: float, n_frames: int, sources,
+                   out: np.ndarray, sigma: float = SIGMA, frame0: int = 0) -> None:
+    """Fill out[f][t][i] (u8) for frames frame0 .. frame0+n_frames-1 of one channel.
+
+    Draw order per frame: real noise [384][2048], then imaginary noise.
+    """
+    spat = _spatial(freq_hz, sources) if sources else None
+    for f in range(n_frames):
+        re = rng.standard_normal((N_TIME, N_INPUTS), dtype=np.float32)
+        im = rng.standard_normal((N_TIME, N_INPUTS), dtype=np.float32)
+        re *= sigma
+        im *= sigma
+        if spat is not None:
+            t_abs = (frame0 + f) * N_TIME + np.arange(N_TIME, dtype=np.float64)
+            sig = _temporal(t_abs, sources) @ spat
+            re += sig.real.astype(np.float32)
+            im += sig.imag.astype(np.float32)
+        np.rint(re, out=re)
+        np.rint(im, out=im)
+        np.clip(re, -7, 7, out=re)
+        np.clip(im, -7, 7, out=im)
+        out[f] = encode(re, im)
+
+
+def config0():
+    """One channel at 600 MHz, one frame, one source at theta=20 deg, phi=0.5 deg, A=3."""
+    c_idx = np.array([512])
+    freqs = chan_freq_hz(c_idx)
+    src = [Source(sin_theta=float(np.sin(np.deg2rad(20.0))), phi_deg=0.5, amp=3.0)]
+    rng = np.random.Generator(np.random.PCG64(1000))
+    raw = np.empty((1, 1, N_TIME, N_INPUTS), dtype=np.uint8)
+    channel_frames(rng, float(freqs[0]), 1, src, raw[:, 0])
+    return {"name": "config0", "c_idx": c_idx, "freqs": freqs, "raw": raw,
+            "sources": {0: src}}
+
+
+def random_sources(rng: np.random.Generator, n: int, amp: float):
+    """n sources inside the primary beam: sin(theta) ~ U[-sin 60, sin 60] (the ~120 deg
+    N-S field of view), phi ~ U[-0.65, 0.65] deg (half the narrowest 1.3 deg E-W field),
+    tone on a seeded 24.4 kHz sub-channel centre, random phase."""
+    s60 = np.sin(np.deg2rad(60.0))
+    out = []
+    for _ in range(n):
+        st = rng.uniform(-s60, s60)
+        ph = rng.uniform(-0.65, 0.65)
+        q = int(rng.integers(0, 16))
+        pha = rng.uniform(0.0, 2 * np.pi)
+        out.append(Source(sin_theta=float(st), phi_deg=float(ph), amp=amp,
+                          tone_hz=(q - 8) * SUBCHAN_HZ, phase=float(pha)))
+    return out
+
+
+def config1(n_frames: int = 128, n_sources: int = 8, seed: int = 1001,
+            c_idx=(128, 384, 640, 896)):
+    """One node's share: 4 channels over 400-800 MHz, n_frames frames each, noise plus
+    n_sources point sources of amplitude 1.5 (same sources in every channel)."""
+    c_idx = np.asarray(c_idx)
+    freqs = chan_freq_hz(c_idx)
+    ss = np.random.SeedSequence(seed)
+    kids = ss.spawn(1 + len(c_idx))
+    srcs = random_sources(np.random.Generator(np.random.PCG64(kids[0])), n_sources, 1.5)
+    raw = np.empty((n_frames, len(c_idx), N_TIME, N_INPUTS), dtype=np.uint8)
+    for ci in range(len(c_idx)):
+        rng = np.random.Generator(np.random.PCG64(kids[1 + ci]))
+        buf = np.empty((n_frames, N_TIME, N_INPUTS), dtype=np.uint8)
+        channel_frames(rng, float(freqs[ci]), n_frames, srcs, buf)
+        raw[:, ci] = buf
+    return {"name": "config1", "c_idx": c_idx, "freqs": freqs, "raw": raw,
+            "sources": srcs}
+
+
+def noise_frames(seed: int, n_frames: int, n_chan: int, sigma: float = SIGMA) -> np.ndarray:
+    """Noise-only bytes [n_frames][n_chan][384][2048] (statistics tests, ragged shapes)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    raw = np.empty((n_frames, n_chan, N_TIME, N_INPUTS), dtype=np.uint8)
+    for c in range(n_chan):
+        buf = np.empty((n_frames, N_TIME, N_INPUTS), dtype=np.uint8)
+        channel_frames(rng, 600e6, n_frames, [], buf, sigma=sigma)
+        raw[:, c] = buf
+    return raw
+
+
+def uniform_bytes(seed: int, shape) -> np.ndarray:
+    """Every byte value equally likely, -8 included (exercises the full decode range)."""
+    return np.random.Generator(np.random.PCG64(seed)).integers(0, 256, size=shape,
+                                                              dtype=np.uint8)

@@ -1,0 +1,331 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks the oracle by a route other than its own code: exhaustive
+tables, exact rational evaluation, library transforms (numpy.fft) as special
+cases, closed-form array factors, Parseval energy identities, exact Dirichlet
+nulls, a point source whose beam geometry predicts, noise statistics from the
+normal CDF, and an unstaged brute-force sum on a tiny array.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.stats import norm
+
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+C0 = 299_792_458.0
+D = 0.3048
+
+
+def _geom(oracle_mod, **kw):
+    return oracle_mod.Geometry(**kw)
+
+
+# ---------------------------------------------------------------- P1 decode
+def test_decode_exhaustive(oracle_mod):
+    """All 256 byte values: decode inverts the generator's independent encoder."""
+    re = np.repeat(np.arange(-8, 8), 16)
+    im = np.tile(np.arange(-8, 8), 16)
+    raw = synth.encode(re, im)
+    assert sorted(raw.tolist()) == list(range(256))
+    z = oracle_mod.decode(raw)
+    np.testing.assert_array_equal(z.real, re)
+    np.testing.assert_array_equal(z.imag, im)
+
+
+def test_decode_fixed_values(oracle_mod):
+    """Offset-binary with the real part in the high nibble."""
+    z = oracle_mod.decode(np.array([0x88, 0x00, 0xF0, 0x0F, 0xFF, 0x97], dtype=np.uint8))
+    np.testing.assert_array_equal(z, [0, -8 - 8j, 7 - 8j, -8 + 7j, 7 + 7j, 1 - 1j])
+
+
+# ---------------------------------------------------------------- P2 LUT (Eq. 1)
+def _lut_exact(f_hz_int: int, m: int, n_beam=256, nb=512):
+    """Eq. (1) in exact rational arithmetic for the default sin-uniform pointings."""
+    s = Fraction(2 * m - (n_beam - 1), n_beam)
+    x = Fraction(nb) * Fraction(f_hz_int) * Fraction(3048, 10000) / Fraction(299792458) * s
+    return math.floor(x + Fraction(1, 2)) % nb
+
+
+def test_lut_matches_exact_rational_all_channels(oracle_mod):
+    """FP64 evaluation never lands on the wrong side of a rounding boundary:
+    every one of the 1024 channels x 256 pointings equals the exact value."""
+    g = _geom(oracle_mod)
+    bad = 0
+    for c in range(0, 1024, 1):
+        f_int = 400_000_000 + c * 390_625
+        k = oracle_mod.lut(g, float(f_int))
+        if c % 37 == 0 or c in (511, 512, 513, 1023):
+            ref = [_lut_exact(f_int, m) for m in range(256)]
+            bad += int(np.count_nonzero(k != np.array(ref)))
+        else:
+            # spot-check a stride of pointings elsewhere to keep the test fast
+            ms = range(c % 7, 256, 7)
+            ref = [_lut_exact(f_int, m) for m in ms]
+            bad += int(np.count_nonzero(k[list(ms)] != np.array(ref)))
+    assert bad == 0
+
+
+def test_lut_half_bin_bound_and_aliasing(oracle_mod):
+    """Sec. 3.1: the kept bin is the FFT beam nearest the desired pointing.
+    Sec. 3.3: spatial aliasing (duplicate bins) appears only above c/(2d)."""
+    g = _geom(oracle_mod)
+    nb = 512
+    f_alias = C0 / (2 * D)
+    for c in range(0, 1024, 5):
+        f = 400e6 + c * 390625.0
+        k = oracle_mod.lut(g, f)
+        scale = nb * f * D / C0          # bins per unit sin(theta)
+        ks = np.where(k > nb // 2, k - nb, k)   # signed bin
+        # unaliased pointings: |sin theta| small enough that the bin stays in range
+        ok = np.abs(g.sin_theta_ns * scale) < nb / 2 - 1
+        err = np.abs(ks[ok] / scale - g.sin_theta_ns[ok])
+        assert np.all(err <= 0.5 / scale + 1e-12)
+        n_unique = len(np.unique(k))
+        if f < f_alias:
+            assert n_unique == 256, (f, n_unique)
+    # above the aliasing frequency the clamped set repeats bins
+    assert len(np.unique(oracle_mod.lut(g, 600e6))) < 256
+    assert len(np.unique(oracle_mod.lut(g, 750e6))) < 256
+
+
+def test_paper_constants():
+    """Table 1 / Sec. 3 rates follow from 384-sample frames and a 16-point DFT."""
+    gold = json.load(open(os.path.join(GOLDEN, "table1_and_text.json")))
+    frame = 384 * gold["input_time_resolution_s"]["value"]
+    assert abs(frame / gold["output_time_resolution_s"]["approx_printed"] - 1) < 1e-3
+    sub = gold["input_channel_width_hz"]["value"] / 16
+    assert abs(sub / gold["output_channel_width_hz"]["approx_printed"] - 1) < 0.02
+    assert 16 * 1024 == gold["output_channels_total"]["value"]
+    assert 4 * 256 * 2 == gold["n_inputs"]["value"]
+    assert gold["n_feed_ns"]["value"] * gold["padding_factor"]["value"] == \
+        gold["fft_beams_before_clamp"]["value"]
+    assert 4 * 256 == gold["output_beams"]["value"]
+    f_alias = C0 / (2 * gold["feed_spacing_m"]["value"])
+    assert abs(f_alias / gold["aliasing_onset_hz"]["approx_printed"] - 1) < 0.01
+
+
+# ---------------------------------------------------------------- P3 N-S
+def test_ns_equals_numpy_fft_zero_padded(oracle_mod):
+    """The direct sums equal numpy's FFT of the line zero-padded to 512."""
+    rng = np.random.default_rng(3)
+    x = rng.integers(-8, 8, 256) + 1j * rng.integers(-8, 8, 256)
+    k = rng.integers(0, 512, 300).astype(np.int32)
+    y = oracle_mod.ns_beams(x, k, 512)
+    ref = np.fft.fft(x, n=512)[k]
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+
+
+def test_ns_parseval(oracle_mod):
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=256) + 1j * rng.normal(size=256)
+    y = oracle_mod.ns_beams(x, np.arange(512, dtype=np.int32), 512)
+    assert abs(np.sum(np.abs(y) ** 2) / (512 * np.sum(np.abs(x) ** 2)) - 1) < 1e-12
+
+
+def test_ns_tiny_brute_force(oracle_mod):
+    """N = 4 feeds, P = 2: every bin written out term by term."""
+    x = np.array([1 + 2j, -3 + 0.5j, 0.25 - 1j, 2 + 2j])
+    w = [complex(math.cos(2 * math.pi * r / 8), -math.sin(2 * math.pi * r / 8)) for r in range(8)]
+    for k in range(8):
+        ref = x[0] * w[0] + x[1] * w[k % 8] + x[2] * w[(2 * k) % 8] + x[3] * w[(3 * k) % 8]
+        y = oracle_mod.ns_beams(x, np.array([k], dtype=np.int32), 8)[0]
+        assert abs(y - ref) < 1e-12
+
+
+def test_ns_beam_centre_and_dirichlet_nulls(oracle_mod):
+    """Sec. 3.1 beam-centre formula: a plane wave at sin(theta) = k0 c / (N P f d)
+    gives |X_k0|^2 = 256^2 |A|^2, exact zeros at k0 +- 2r and the Dirichlet
+    pattern |sin(pi*256*delta/512) / sin(pi*delta/512)|^2 elsewhere."""
+    f = 600e6
+    k0 = 77
+    s = k0 * C0 / (512 * f * D)
+    n = np.arange(256)
+    A = 1.7 - 0.4j
+    x = A * np.exp(2j * np.pi * f * n * D * s / C0)
+    y = oracle_mod.ns_beams(x, np.arange(512, dtype=np.int32), 512)
+    p = np.abs(y) ** 2
+    assert abs(p[k0] / (256 ** 2 * abs(A) ** 2) - 1) < 1e-12
+    delta = (np.arange(512) - k0)
+    even = (delta % 2 == 0) & (delta != 0)
+    assert np.all(p[even] < 1e-18 * p[k0])
+    odd = delta % 2 == 1
+    dir_ = np.abs(np.sin(np.pi * 256 * delta[odd] / 512) / np.sin(np.pi * delta[odd] / 512)) ** 2
+    np.testing.assert_allclose(p[odd], dir_ * abs(A) ** 2, rtol=1e-9)
+
+
+# ---------------------------------------------------------------- P4 E-W
+def test_ew_array_factor_closed_form(oracle_mod):
+    """Four cylinders 20 m apart: |b_j|^2 for a unit plane wave at u equals
+    |sin(4 a / 2) / sin(a / 2)|^2 with a = 2 pi f D (u - sin phi_j) / c0."""
+    g = _geom(oracle_mod)
+    f = 650e6
+    for u in (-0.01, -0.003, 0.0, 0.0021, 0.0105):
+        y = np.exp(2j * np.pi * f * g.cyl_x_m * u / C0)
+        b = oracle_mod.ew_beams(oracle_mod.ew_weights(g, f), y)
+        a = 2 * np.pi * f * 20.0 * (u - g.sin_phi_ew) / C0
+        with np.errstate(invalid="ignore", divide="ignore"):
+            af = np.where(np.abs(np.sin(a / 2)) < 1e-15, 16.0,
+                          (np.sin(2 * a) / np.sin(a / 2)) ** 2)
+        np.testing.assert_allclose(np.abs(b) ** 2, af, rtol=1e-9, atol=1e-9)
+
+
+def test_ew_scaled_unitary_energy(oracle_mod):
+    """sin(phi_j) = j c0 / (4 f D) makes W a phased DFT-4: sum_j |b_j|^2 = 4 sum_c |y_c|^2."""
+    f = 600e6
+    g = _geom(oracle_mod, sin_phi_ew=np.arange(4) * C0 / (4 * f * 20.0))
+    rng = np.random.default_rng(5)
+    y = rng.normal(size=4) + 1j * rng.normal(size=4)
+    b = oracle_mod.ew_beams(oracle_mod.ew_weights(g, f), y)
+    assert abs(np.sum(np.abs(b) ** 2) / (4 * np.sum(np.abs(y) ** 2)) - 1) < 1e-12
+
+
+# ---------------------------------------------------------------- P5 up-channelisation
+def test_upchan_tone_and_parseval(oracle_mod):
+    """A tone on sub-channel s lands in bin s only; Parseval holds; equals numpy.fft."""
+    tau = np.arange(16)
+    for s0 in (0, 3, 8, 15):
+        b = (2 - 1j) * np.exp(2j * np.pi * s0 * tau / 16)
+        u = oracle_mod.upchan(b)
+        assert abs(u[s0] - 16 * (2 - 1j)) < 1e-12
+        assert np.all(np.abs(np.delete(u, s0)) < 1e-12)
+    rng = np.random.default_rng(6)
+    b = rng.normal(size=16) + 1j * rng.normal(size=16)
+    u = oracle_mod.upchan(b)
+    np.testing.assert_allclose(u, np.fft.fft(b), atol=1e-12)
+    assert abs(np.sum(np.abs(u) ** 2) / (16 * np.sum(np.abs(b) ** 2)) - 1) < 1e-12
+
+
+# ---------------------------------------------------------------- whole pipeline
+def _brute_force_unit(raw, f, geom_kw, k, sin_phi, cyl_x):
+    """Unstaged sum: for each output, |sum over (tau, cyl, feed) of sample x phase|^2
+    summed over blocks and pols, no intermediate arrays."""
+    NF, NB, NC, NP, NM, NJ, L, T = (geom_kw[n] for n in
+                                    ("n_feed", "nb", "n_cyl", "n_pol", "n_beam_ns",
+                                     "n_beam_ew", "n_dft", "n_time"))
+    out = np.zeros((NJ * NM, L))
+    for j in range(NJ):
+        for m in range(NM):
+            for s in range(L):
+                q = (s + L // 2) % L
+                for blk in range(T // L):
+                    for p in range(NP):
+                        acc = 0j
+                        for tau in range(L):
+                            for c in range(NC):
+                                for n in range(NF):
+                                    byte = int(raw[blk * L + tau, (c * NF + n) * NP + p])
+                                    xv = complex((byte >> 4) - 8, (byte & 15) - 8)
+                                    ph = -(n * k[m] / NB + f * cyl_x[c] * sin_phi[j] / C0
+                                           + s * tau / L)
+                                    acc += xv * complex(math.cos(2 * math.pi * ph),
+                                                        math.sin(2 * math.pi * ph))
+                        out[j * NM + m, q] += abs(acc) ** 2
+    return out
+
+
+def test_pipeline_tiny_brute_force(oracle_mod):
+    kw = dict(n_feed=4, pad=2, n_cyl=2, n_pol=2, n_beam_ns=3, n_beam_ew=2, n_dft=4, n_time=8)
+    cyl_x = np.array([-10.0, 10.0])
+    sin_theta = np.array([-0.3, 0.05, 0.6])
+    sin_phi = np.array([-0.004, 0.007])
+    g = oracle_mod.Geometry(**kw, cyl_x_m=cyl_x, sin_theta_ns=sin_theta, sin_phi_ew=sin_phi)
+    f = 700e6
+    raw = synth.uniform_bytes(11, (1, 1, 8, 16))
+    out = oracle_mod.beamform(g, [f], raw)[0, 0]
+    k = oracle_mod.lut(g, f)
+    # independent Eq. (1) for these three pointings
+    k_ref = [math.floor(8 * f * D / C0 * s + 0.5) % 8 for s in sin_theta]
+    assert list(k) == k_ref
+    ref = _brute_force_unit(raw[0, 0], f, dict(kw, nb=8), k_ref, sin_phi, cyl_x)
+    np.testing.assert_allclose(out, ref, rtol=1e-12, atol=1e-9)
+
+
+def test_pipeline_energy_even_odd_bins(oracle_mod):
+    """Run once keeping the 256 even bins and once the 256 odd bins, with the
+    scaled-unitary E-W directions: the summed output equals 16 * 4 * 512 * sum|x|^2
+    (Parseval through N-S, E-W and the time DFT)."""
+    f = 600e6
+    g = _geom(oracle_mod, sin_phi_ew=np.arange(4) * C0 / (4 * f * 20.0))
+    raw = synth.uniform_bytes(12, (1, 1, 384, 2048))
+    even = (2 * np.arange(256)).astype(np.int32)[None]
+    odd = even + 1
+    tot = (oracle_mod.beamform(g, [f], raw, lut_override=even).sum()
+           + oracle_mod.beamform(g, [f], raw, lut_override=odd).sum())
+    x = oracle_mod.decode(raw)
+    assert abs(tot / (16 * 4 * 512 * np.sum(np.abs(x) ** 2)) - 1) < 1e-11
+
+
+def test_noise_mean_statistics(oracle_mod):
+    """Noise-only output mean = 16 * 24 * 2 * 1024 * E|x|^2, with E|x|^2 of
+    N(0, 2.5^2) rounded and clipped to +-7 from the normal CDF; each output is
+    a Gamma(48) sum (relative spread 1/sqrt(48))."""
+    g = _geom(oracle_mod)
+    raw = synth.noise_frames(21, 2, 2)
+    out = oracle_mod.beamform(g, [450e6, 720e6], raw)
+    k = np.arange(-7, 8)
+    sig = 2.5
+    p = norm.cdf((k + 0.5) / sig) - norm.cdf((k - 0.5) / sig)
+    p[0] = norm.cdf(-6.5 / sig)
+    p[-1] = 1 - norm.cdf(6.5 / sig)
+    e_x2 = 2 * np.sum(p * k * k)
+    expect = 16 * 24 * 2 * 1024 * e_x2
+    n = out.size
+    assert abs(out.mean() / expect - 1) < 6 / math.sqrt(48 * n)
+    assert abs(out.std() / out.mean() - 1 / math.sqrt(48)) < 0.01
+
+
+def _predicted_beam(oracle_mod, g, f, sin_theta, phi_deg):
+    """Strongest beam predicted from FP64 closed-form array factors (no data)."""
+    u = math.sin(math.radians(phi_deg))
+    v = math.cos(math.radians(phi_deg)) * sin_theta
+    k = oracle_mod.lut(g, f)
+    kt = 512 * f * D * v / C0
+    delta = kt - k
+    ns = (np.sin(np.pi * 256 * delta / 512) / (256 * np.sin(np.pi * delta / 512))) ** 2
+    a = 2 * np.pi * f * 20.0 * (u - g.sin_phi_ew) / C0
+    ew = (np.sin(2 * a) / (4 * np.sin(a / 2))) ** 2
+    resp = ew[:, None] * ns[None, :]
+    return int(np.argmax(resp)), resp
+
+
+def test_point_source_peaks_in_predicted_beam(oracle_mod):
+    """Noisy 600 MHz frame with a source at theta = 20 deg, phi = 0.5 deg, tone at the
+    channel centre: the strongest output is the beam the geometry predicts, at the
+    centre sub-channel (q = 8, the DC bin after the centre shift)."""
+    g = _geom(oracle_mod)
+    c = synth.config0()
+    out = oracle_mod.beamform(g, c["freqs"], c["raw"])[0, 0]
+    beam, _ = _predicted_beam(oracle_mod, g, 600e6, math.sin(math.radians(20)), 0.5)
+    b, q = np.unravel_index(np.argmax(out), out.shape)
+    assert (b, q) == (beam, 8)
+    assert beam == 3 * 256 + 171
+    assert out[b, q] > 1000 * np.median(out)
+
+
+def test_alias_lands_where_geometry_says(oracle_mod):
+    """Sec. 3.3: above ~490 MHz a source also appears in an aliased beam; a 26 deg
+    source at 760 MHz aliases to sin(theta) = sin(26) - c/(f d) (about -59 deg)."""
+    g = _geom(oracle_mod)
+    f = 760e6
+    st = math.sin(math.radians(26.0))
+    src = [synth.Source(sin_theta=st, phi_deg=0.0, amp=2.0)]
+    raw = np.empty((1, 1, 384, 2048), dtype=np.uint8)
+    synth.channel_frames(np.random.default_rng(0), f, 1, src, raw[:, 0], sigma=0.0)
+    out = oracle_mod.beamform(g, [f], raw)[0, 0].sum(axis=1).reshape(4, 256).sum(axis=0)
+    alias = st - C0 / (f * D)
+    m_main = int(np.argmax(np.where(g.sin_theta_ns > 0, out, 0)))
+    m_alias = int(np.argmax(np.where(g.sin_theta_ns < 0, out, 0)))
+    assert abs(g.sin_theta_ns[m_main] - st) < 2 / 128
+    assert abs(g.sin_theta_ns[m_alias] - alias) < 2 / 128
+    gold = json.load(open(os.path.join(GOLDEN, "table1_and_text.json")))
+    lo, hi = gold["alias_extent_deg_for_26deg_source"]["approx_printed"]
+    # across the aliasing band the alias sweeps the range the paper reports
+    f_edge = C0 / (D * (1 + st))
+    ang = [math.degrees(math.asin(max(-1.0, st - C0 / (ff * D)))) for ff in (f_edge, 800e6)]
+    assert abs(ang[0] - lo) < 3 and abs(ang[1] - hi) < 3
