@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the hybrid FFT beamformer on one MI355X.
+
+A step is one beamform_frame launch over one batch: the bench workload is 4
+frequency channels (450, 550, 650, 750 MHz) x 128 frames of 384 samples x
+2048 inputs of 4+4-bit seeded synthetic noise plus 8 point sources (402.7 MB
+resident in HBM before timing), producing 1024 beams x 16 sub-channels per
+channel-frame.  Value = channel-frames per second x 0.98304 ms = frequency
+channels the GPU sustains in real time.
+
+Prints ONE JSON line (rank 0).  Multi-GPU runs are not part of this build:
+--gpus above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frequency channels sustained in real time, FP32 vs FP16-MFMA; p99 frame latency"
+FRAME_S = 384 * 2.56e-6                 # 0.98304 ms
+BYTES_PER_UNIT = 384 * 2048 + 1024 * 16 * 4  # 851,968 algorithmic HBM bytes per channel-frame
+# Conventional flop count per sample (5 N log2 N FFTs): N-S 8 x 512-point = 184,320,
+# E-W 1024 beams x 2 pols x 4 complex MACs = 65,536, 2048 16-point DFTs = 40,960,
+# detection 8,192.  Times 384 samples per channel-frame.
+FLOPS_PER_UNIT = {"fp32": 384 * (184_320 + 65_536 + 40_960 + 8_192)}
+PEAK = {"fp32": (157.3, "TFLOP/s")}     # MI355X FP32 vector peak (published)
+HBM_PEAK_GBS = 8000.0
+KERNEL_NAME = {"fp32": "bf_fp32_kernel"}
+KERNEL_SOURCES = {"fp32": ["paper_1702_04728_amd/csrc/bf_fp32.hip",
+                           "paper_1702_04728_amd/csrc/bf_internal.h"]}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash(path_key: str) -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[path_key]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_from_profiles(path_key: str, units: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when there is none or the kernel source changed since it was taken."""
+    p = os.path.join(ROOT, "profiles", "traffic_%s_config1.json" % path_key)
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("source_sha256") != source_hash(path_key) or d.get("units_per_dispatch") != units:
+        return None
+    return float(d["fetch_kib"] * 1024 * d["fetch_scale"] + d["write_kib"] * 1024 * d["write_scale"])
+
+
+def cpu_baseline(raw, freqs, budget_s: float):
+    """The FP64 oracle on a bounded sample of the same workload (whole channel-frames,
+    frame-major order), all host threads, until ~budget_s of wall time."""
+    import oracle
+    oracle.build()
+    g = oracle.Geometry()
+    n_frames, n_chan = raw.shape[0], raw.shape[1]
+    threads = oracle.max_threads()
+    all_units = [(f, c) for f in range(n_frames) for c in range(n_chan)]
+    done = 0
+    t0 = time.perf_counter()
+    while done < len(all_units) and time.perf_counter() - t0 < budget_s:
+        batch = all_units[done:done + threads]
+        oracle.beamform(g, freqs, raw, units=batch, n_threads=threads)
+        done += len(batch)
+    dt = time.perf_counter() - t0
+    rate = done / dt
+    return {"value": rate * FRAME_S, "unit": "channels (real time)", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d of %d channel-frames of the same workload (frame-major), %.1f s, "
+                      "%.3f channel-frames/s" % (done, len(all_units), dt, rate)}
+
+
+def copy_probe(torch, mib: int, reps: int):
+    """A plain device-to-device copy of known size, for counter calibration runs."""
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy probe: %d x %d MiB" % (reps, mib))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--frames", type=int, default=128)
+    ap.add_argument("--precision", default="fp32", choices=["fp32"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(channels shard across GPUs with no exchange; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1702_04728_amd as bf
+
+    bf.load_library()
+    log("generating workload (4 channels x %d frames)..." % args.frames)
+    t0 = time.perf_counter()
+    cfg = synth.config1(n_frames=args.frames)
+    raw_np, freqs = cfg["raw"], cfg["freqs"]
+    log("generated in %.1f s" % (time.perf_counter() - t0))
+    n_frames, n_chan = raw_np.shape[0], raw_np.shape[1]
+    units = n_frames * n_chan
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    raw = torch.from_numpy(raw_np).to(dev)
+    beam = bf.Beamformer(freqs, precision=args.precision)
+    out = torch.empty(beam.out_shape(n_frames), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        beam.frame(raw, out)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        starts[i].record(stream)
+        beam.frame(raw, out)
+        ends[i].record(stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall0
+    total_ms = ev0.elapsed_time(ev1)
+    per = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    ms_step = total_ms / args.steps
+    log("timed %d steps: %.4f ms/step (events), wall %.3f s" % (args.steps, ms_step, wall))
+
+    if args.copy_probe_mib:
+        copy_probe(torch, args.copy_probe_mib, 3)
+
+    unit_per_s = units / (ms_step * 1e-3)
+    value = unit_per_s * FRAME_S
+    kern_s = float(np.mean(per)) * 1e-3
+    flops = FLOPS_PER_UNIT[args.precision] * units
+    peak, punit = PEAK[args.precision]
+    achieved = flops / kern_s / 1e12
+    traffic = traffic_from_profiles(args.precision, units)
+    res = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "channels (real time)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "config1: 4 channels (450/550/650/750 MHz) x %d frames of 384 "
+                               "samples x 2048 inputs, 4+4-bit noise + 8 point sources; "
+                               "1024 beams x 16 sub-channels per channel-frame" % n_frames,
+                   "path": "fp32_fft", "channel_frames_per_step": units,
+                   "input_bytes_per_step": int(raw_np.nbytes)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                     "unit": punit, "frac": round(achieved / peak, 4),
+                     "traffic": traffic, "kernel": KERNEL_NAME[args.precision],
+                     "flops_per_launch": flops},
+        "hbm": {"achieved_GBs": round(BYTES_PER_UNIT * units / kern_s / 1e9, 1),
+                "peak_GBs": HBM_PEAK_GBS,
+                "frac": round(BYTES_PER_UNIT * units / kern_s / 1e9 / HBM_PEAK_GBS, 4),
+                "bytes_per_launch": BYTES_PER_UNIT * units},
+        "input_GBs": round(raw_np.nbytes / (ms_step * 1e-3) / 1e9, 1),
+        "step_ms_p50": round(float(np.percentile(per, 50)), 5),
+        "step_ms_p99": round(float(np.percentile(per, 99)), 5),
+        "frames_per_step_per_channel": n_frames,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)...")
+        res["cpu_baseline"] = cpu_baseline(raw_np, freqs, args.cpu_seconds)
+    else:
+        res["cpu_baseline"] = None
+    beam.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,139 @@
+/*
+ * beamform.h -- C ABI of the MI355X hybrid FFT beamformer (libbeamform.so).
+ *
+ * Implements the CHIME/FRB fan-beam hot path of Ng et al., "CHIME FRB: An
+ * application of FFT beamforming for a radio telescope" (arXiv:1702.04728):
+ * per frequency channel and per 0.983 ms frame of 384 samples,
+ *   - decode 4+4-bit complex voltages of 2048 inputs (Sec. 2, Table 1);
+ *   - N-S beams: 256-feed lines zero-padded to 512 and Fourier transformed,
+ *     keeping per channel the 256 bins nearest the desired pointings
+ *     (Sec. 3.1, Eqs. (1)-(2));
+ *   - 4 E-W beams by exact phasing across the 4 cylinders (Sec. 3, Sec. 3.1);
+ *   - up-channelisation by a 16-point DFT in time, 390.625 kHz -> 24.4 kHz
+ *     (Sec. 3, Sec. 3.2);
+ *   - Stokes I (|X|^2 + |Y|^2) integrated over the 24 16-sample blocks of the
+ *     frame (Sec. 3, Table 1).
+ *
+ * Conventions (readings of what the paper leaves open):
+ *   input  u8 in[frame][chan][t < n_time][i < 2048], i = (cyl*256+feed)*2+pol,
+ *          byte = ((re + 8) << 4) | (im + 8)  (high nibble real);
+ *   output f32 out[frame][chan][beam < 1024][q < 16], beam = j*256 + m
+ *          (E-W beam j, N-S beam m), sub-channel q holds time-DFT bin
+ *          s = (q + 8) mod 16, so q = 8 is the channel centre; no normalisation;
+ *   Eq. (1) index k_m = floor(512 f d sin(theta_m) / c + 0.5) mod 512 (FP64);
+ *   E-W weight W[j][c] = exp(-2 pi i f x_c sin(phi_j) / c), forward
+ *   transforms exp(-2 pi i ...).
+ *
+ * Memory and ownership: all data pointers passed to beamform_frame are DEVICE
+ * pointers owned by the caller; the library never frees them.  Arrays inside
+ * bf_config are HOST pointers, copied during beamform_init (the caller may
+ * free them afterwards).  The plan owns its device tables; beamform_destroy
+ * synchronises the plan's device and frees them.
+ *
+ * Streams: `stream` arguments are hipStream_t values passed as void* (NULL is
+ * the null stream).  Work is enqueued asynchronously; outputs are valid once
+ * the stream reaches the enqueued work.
+ *
+ * Errors: every call returns an int32 status (BF_OK = 0, negative on error).
+ * No exception or process exit crosses this interface.  Launch failures are
+ * reported by the call that launched; asynchronous device faults surface as
+ * BF_E_DEVICE from a later call.  beamform_strerror() gives a static string,
+ * beamform_last_error() the plan's last detailed message.  A plan is not
+ * thread-safe: use one plan per host thread.
+ */
+#ifndef BEAMFORM_H
+#define BEAMFORM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BF_OK 0
+#define BF_E_INVAL (-1)       /* bad argument, size or pointer */
+#define BF_E_NOMEM (-2)       /* host or device allocation failed */
+#define BF_E_DEVICE (-3)      /* HIP runtime / kernel failure */
+#define BF_E_STATE (-4)       /* call not valid for the plan's state */
+#define BF_E_UNSUPPORTED (-5) /* valid request this build does not implement */
+
+typedef struct bf_plan bf_plan; /* opaque, library-owned */
+
+/* Arithmetic of the N-S transform.  BF_FP32_FFT: FP32 radix FFT (the baseline,
+ * <= 1e-5 relative power error against an FP64 evaluation).  BF_FP16_MFMA:
+ * four-step 512 = 32 x 16 DFT on FP16 matrix cores with FP32 accumulation. */
+typedef enum { BF_FP32_FFT = 0, BF_FP16_MFMA = 1 } bf_precision;
+
+typedef struct {
+    int32_t n_cyl;      /* cylinders: must be 4 */
+    int32_t n_feed;     /* N-S feeds per cylinder (N): must be 256 */
+    int32_t n_pol;      /* polarisations: must be 2 */
+    int32_t pad;        /* zero-padding factor P: must be 2 (Sec. 3.1) */
+    int32_t n_beam_ns;  /* kept N-S beams: must be 256 */
+    int32_t n_beam_ew;  /* E-W beams: must be 4 */
+    int32_t n_upchan;   /* time-DFT length: must be 16 */
+    int32_t n_time;     /* samples per frame: a positive multiple of 16 (384 = 0.983 ms) */
+    double feed_spacing_m;      /* N-S feed spacing d (0.3048 m, Sec. 1) */
+    double c0;                  /* speed of light in m/s (299792458) */
+    const double *cyl_x_m;      /* [n_cyl] E-W cylinder positions; NULL: (c - 1.5) * 20 m */
+    const double *sin_theta_ns; /* [n_beam_ns] desired N-S pointings sin(theta_m);
+                                   NULL: (m - 127.5) / 128 */
+    const double *sin_phi_ew;   /* [n_beam_ew] E-W beam directions sin(phi_j);
+                                   NULL: sin((j - 1.5) * 0.4 deg) */
+    const int32_t *lut_override;/* [n_chan][n_beam_ns] bins in [0, 512) used instead of
+                                   Eq. (1), or NULL */
+    int32_t precision;          /* bf_precision */
+    int32_t reserved;           /* must be 0 */
+} bf_config;
+
+/* Fill *cfg with the defaults above (sizes 4/256/2/2/256/4/16/384, d = 0.3048 m,
+ * c0 = 299792458, NULL tables, BF_FP32_FFT).  Host only, no device call. */
+int32_t beamform_default_config(bf_config *cfg);
+
+/* Eq. (1)-(2) (Sec. 3.1): the kept FFT bin of every desired N-S pointing for
+ * each channel, k_m = floor(N P f d sin(theta_m) / c + 0.5) mod (N P),
+ * evaluated in FP64 (or cfg->lut_override copied).  chan_freq_hz: host
+ * [n_chan]; out: host int32 [n_chan][n_beam_ns].  Host only, no device call. */
+int32_t beamform_compute_lut(const bf_config *cfg, const double *chan_freq_hz,
+                             int32_t n_chan, int32_t *out);
+
+/* Create a plan for n_chan channels with centre frequencies chan_freq_hz
+ * (host FP64 [n_chan], Hz) on the current HIP device: validates cfg, computes
+ * in FP64 the Eq. (1) bin table, the E-W phases W[chan][j][c] and the FFT
+ * twiddles, rounds each once to the kernel precision and uploads them on
+ * `stream`.  *out_plan is set only on success. */
+int32_t beamform_init(const bf_config *cfg, const double *chan_freq_hz, int32_t n_chan,
+                      void *stream, bf_plan **out_plan);
+
+/* Beamform n_frames frames of all the plan's channels (the full hot path:
+ * decode, N-S beams, E-W beams, 16-point up-channelisation, Stokes I,
+ * integration over the frame).
+ *   d_in : device u8  [n_frames][n_chan][n_time][2048], 16-byte aligned;
+ *   d_out: device f32 [n_frames][n_chan][1024][16], 16-byte aligned, fully
+ *          overwritten (no accumulation across calls).
+ * n_frames = 0 is a valid no-op.  Asynchronous on `stream`. */
+int32_t beamform_frame(bf_plan *plan, const uint8_t *d_in, int32_t n_frames, float *d_out,
+                       void *stream);
+
+/* Copy the plan's bin table to host int32 [n_chan][n_beam_ns] (synchronous). */
+int32_t beamform_get_lut(const bf_plan *plan, int32_t *host_out);
+
+/* Number of channels and samples per frame of a plan. */
+int32_t beamform_plan_info(const bf_plan *plan, int32_t *n_chan, int32_t *n_time,
+                           int32_t *precision);
+
+/* Synchronise the plan's device, free its tables and the plan.  NULL is a no-op. */
+int32_t beamform_destroy(bf_plan *plan);
+
+/* Static description of a status code. */
+const char *beamform_strerror(int32_t status);
+
+/* The plan's last error message ("" if none); NULL plan: the last error of a
+ * failed beamform_init on this thread. */
+const char *beamform_last_error(const bf_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEAMFORM_H */

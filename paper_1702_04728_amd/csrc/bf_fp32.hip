@@ -1,0 +1,362 @@
+// FP32 FFT path of the hybrid beamformer, one fused kernel.
+//
+// What is computed (paper Sec. 3, Sec. 3.1, Sec. 3.2): for every channel-frame
+// (384 samples x 2048 inputs of 4+4-bit complex voltages), Stokes-I power of
+// 1024 beams (256 N-S FFT beams clamped to the desired pointings x 4 E-W beams
+// by exact phasing) in 16 up-channelised sub-channels, integrated over the
+// frame's 24 blocks of 16 samples.
+//
+// All stages are linear up to the detector, and each acts on its own axis:
+// the time DFT on samples, E-W phasing on cylinders, the N-S transform on
+// feeds.  They therefore commute, and this kernel applies them in the order
+// that keeps data on chip: time DFT first (on the raw integer samples), then
+// E-W phasing, then the zero-padded 512-point N-S transform, then |.|^2.
+// Because the clamping only picks which N-S bins become output beams, power
+// is integrated per FFT bin and the Eq. (1) bin table is applied once per
+// frame when the result is written.  The paper's separate transpose kernel
+// disappears: the time axis is consumed while the block is in registers.
+//
+// Decomposition: one workgroup (256 threads) per (channel-frame, s0), where
+// s0 in [0, 4) selects the sub-channels s = s0 + 4*s2 (s2 in [0, 4)).  Per
+// 16-sample block:
+//   A  each thread reads 16 samples of 8 consecutive inputs, forms its four
+//      time-DFT outputs via a radix-4 split (a DFT-4 over the sample stride,
+//      a twiddle, a DFT-4 over the sample phase), writes them to LDS;
+//   B1 each 16-lane group (s2, j) applies E-W weights W[j][c] while reading
+//      the two polarisation lines it owns (lane b holds feeds 16a + b);
+//   B2 each group transforms both lines: 512 = 32 x 16 with the upper half of
+//      the input zero, so step 1 is a pruned 32-point DFT per lane (two 16-point
+//      FFTs), then twiddles w512^(b c), a 16-lane transpose through LDS and a
+//      16-point FFT per lane; |X|^2 of both pols accumulates in registers.
+// After the last block, per-bin powers go through LDS and are gathered by
+// the bin table into out[beam][q].
+#include <hip/hip_runtime.h>
+
+#include "bf_internal.h"
+
+namespace bf {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kXpStride = 17;                    // padded row of a transpose buffer
+constexpr int kXpBuf = 16 * kXpStride;           // float2 per buffer
+constexpr int kUnionF2 = 16 * 2 * kXpBuf;        // 16 groups x {E, O} buffers (8704)
+constexpr int kTF4 = 4 * 1024;                   // time-DFT output: 4 s2 x 1024 float4
+static_assert(kUnionF2 * 8 >= kTF4 * 16, "union region must hold the time-DFT output");
+static_assert(kUnionF2 * 8 >= 16 * 512 * 4, "union region must hold the per-bin powers");
+
+// e^{-2 pi i k / 16} and e^{-2 pi i k / 32} constants.
+constexpr float kC16_1 = 0.92387953251128675613f;  // cos(pi/8)
+constexpr float kS16_1 = 0.38268343236508977173f;  // sin(pi/8)
+constexpr float kR2 = 0.70710678118654752440f;     // cos(pi/4)
+constexpr float kC32_1 = 0.98078528040323044913f;  // cos(pi/16)
+constexpr float kS32_1 = 0.19509032201612826785f;  // sin(pi/16)
+constexpr float kC32_3 = 0.83146961230254523708f;  // cos(3pi/16)
+constexpr float kS32_3 = 0.55557023301960222474f;  // sin(3pi/16)
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 w)
+{
+    return make_float2(fmaf(a.x, w.x, -a.y * w.y), fmaf(a.x, w.y, a.y * w.x));
+}
+// a * c + acc, complex
+__device__ __forceinline__ float2 cmac(float2 acc, float2 a, float2 w)
+{
+    return make_float2(fmaf(a.x, w.x, fmaf(-a.y, w.y, acc.x)), fmaf(a.x, w.y, fmaf(a.y, w.x, acc.y)));
+}
+
+// Multiply by (-i)^K.
+template <int K>
+__device__ __forceinline__ float2 rot(float2 a)
+{
+    constexpr int k = ((K % 4) + 4) % 4;
+    if constexpr (k == 0) return a;
+    else if constexpr (k == 1) return make_float2(a.y, -a.x);
+    else if constexpr (k == 2) return make_float2(-a.x, -a.y);
+    else return make_float2(-a.y, a.x);
+}
+
+// cos and sin of 2 pi k / 32 for k in [0, 8], by symmetry from the table above.
+template <int K>
+__device__ __forceinline__ float2 cs32()
+{
+    static_assert(K >= 0 && K <= 8, "first octant only");
+    if constexpr (K == 0) return make_float2(1.f, 0.f);
+    else if constexpr (K == 1) return make_float2(kC32_1, kS32_1);
+    else if constexpr (K == 2) return make_float2(kC16_1, kS16_1);
+    else if constexpr (K == 3) return make_float2(kC32_3, kS32_3);
+    else if constexpr (K == 4) return make_float2(kR2, kR2);
+    else if constexpr (K == 5) return make_float2(kS32_3, kC32_3);
+    else if constexpr (K == 6) return make_float2(kS16_1, kC16_1);
+    else if constexpr (K == 7) return make_float2(kS32_1, kC32_1);
+    else return make_float2(0.f, 1.f);
+}
+
+// Multiply by w32^K = e^{-2 pi i K / 32}.
+template <int K>
+__device__ __forceinline__ float2 tw32(float2 a)
+{
+    constexpr int k = ((K % 32) + 32) % 32;
+    if constexpr (k % 8 == 0) return rot<k / 8>(a);
+    else if constexpr (k < 8) {
+        const float2 cs = cs32<k>();
+        return cmul(a, make_float2(cs.x, -cs.y));
+    } else {
+        // w32^k = (-i)^(k/8) * w32^(k%8)
+        return rot<k / 8>(tw32<k % 8>(a));
+    }
+}
+
+// Multiply by w16^K.
+template <int K>
+__device__ __forceinline__ float2 tw16(float2 a) { return tw32<2 * K>(a); }
+
+// In-place DFT-4 of (a, b, c, d): X_k = sum_n x_n (-i)^(n k).
+__device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d)
+{
+    const float2 t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), t3 = csub(b, d);
+    a = cadd(t0, t2);
+    c = csub(t0, t2);
+    b = cadd(t1, rot<1>(t3));
+    d = csub(t1, rot<1>(t3));
+}
+
+// In-place 16-point FFT, natural order in and out: v[k] <- sum_a v[a] w16^(a k).
+// Radix 4 x 4: a = 4 a1 + a2, k = k1 + 4 k2.
+__device__ __forceinline__ void fft16(float2 (&v)[16])
+{
+#pragma unroll
+    for (int a2 = 0; a2 < 4; ++a2) dft4(v[a2], v[4 + a2], v[8 + a2], v[12 + a2]);
+    // element [4 k1 + a2] now holds u[a2][k1]; twiddle by w16^(a2 k1)
+    v[5] = tw16<1>(v[5]);
+    v[6] = tw16<2>(v[6]);
+    v[7] = tw16<3>(v[7]);
+    v[9] = tw16<2>(v[9]);
+    v[10] = tw16<4>(v[10]);
+    v[11] = tw16<6>(v[11]);
+    v[13] = tw16<3>(v[13]);
+    v[14] = tw16<6>(v[14]);
+    v[15] = tw16<9>(v[15]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // element [4 k1 + k2] holds V[k1 + 4 k2]: transpose the 4 x 4 index
+    float2 t;
+    t = v[1]; v[1] = v[4]; v[4] = t;
+    t = v[2]; v[2] = v[8]; v[8] = t;
+    t = v[3]; v[3] = v[12]; v[12] = t;
+    t = v[6]; v[6] = v[9]; v[9] = t;
+    t = v[7]; v[7] = v[13]; v[13] = t;
+    t = v[11]; v[11] = v[14]; v[14] = t;
+}
+
+// Orders LDS traffic between the lanes of one wavefront.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Phase A for sub-channel class S0: time-DFT bins s = S0 + 4 s2 of this
+// thread's 8 inputs over one 16-sample block.
+//   y[t1] = sum_t2 x[t1 + 4 t2] (-i)^(t2 S0)      (DFT-4 over the stride)
+//   T[s2] = sum_t1 (y[t1] w16^(t1 S0)) (-i)^(t1 s2)
+template <int S0>
+__device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restrict__ T, int t)
+{
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        float2 o[2][4];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int e = 2 * h + p;  // input 8 t + e: feed 4 (t % 64) + h, pol p
+            float2 x[16];
+#pragma unroll
+            for (int tau = 0; tau < 16; ++tau) {
+                const uint32_t w = (e < 4) ? raw[tau].x : raw[tau].y;
+                const uint32_t byte = (w >> (8 * (e & 3))) & 0xffu;
+                x[tau] = make_float2((float)(byte >> 4) - 8.f, (float)(byte & 15u) - 8.f);
+            }
+            float2 y[4];
+#pragma unroll
+            for (int t1 = 0; t1 < 4; ++t1) {
+                y[t1] = cadd(cadd(x[t1], rot<S0>(x[t1 + 4])),
+                             cadd(rot<2 * S0>(x[t1 + 8]), rot<3 * S0>(x[t1 + 12])));
+            }
+            y[1] = tw16<S0>(y[1]);
+            y[2] = tw16<2 * S0>(y[2]);
+            y[3] = tw16<3 * S0>(y[3]);
+            dft4(y[0], y[1], y[2], y[3]);
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) o[p][s2] = y[s2];
+        }
+        // slot (cyl * 256 + feed) holds both pols of one feed
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2)
+            T[s2 * 1024 + 4 * t + h] = make_float4(o[0][s2].x, o[0][s2].y, o[1][s2].x, o[1][s2].y);
+    }
+}
+
+// Zero-padded 512-point N-S transform of one line held as x[a] = line[16 a + b]
+// by lane b of a 16-lane group; accumulates |X_k|^2 for k = 2 b + r + 32 d into
+// acc[r][d].  bufE / bufO: this group's two transpose buffers.
+__device__ __forceinline__ void ns_line_power(const float2 (&x)[16], float (&acc)[2][16],
+                                              float2* __restrict__ bufE,
+                                              float2* __restrict__ bufO,
+                                              const float2* __restrict__ tw, int b)
+{
+    float2 E[16], O[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a) E[a] = x[a];
+    O[0] = x[0];
+    O[1] = tw32<1>(x[1]);
+    O[2] = tw32<2>(x[2]);
+    O[3] = tw32<3>(x[3]);
+    O[4] = tw32<4>(x[4]);
+    O[5] = tw32<5>(x[5]);
+    O[6] = tw32<6>(x[6]);
+    O[7] = tw32<7>(x[7]);
+    O[8] = tw32<8>(x[8]);
+    O[9] = tw32<9>(x[9]);
+    O[10] = tw32<10>(x[10]);
+    O[11] = tw32<11>(x[11]);
+    O[12] = tw32<12>(x[12]);
+    O[13] = tw32<13>(x[13]);
+    O[14] = tw32<14>(x[14]);
+    O[15] = tw32<15>(x[15]);
+    // step 1: Z[2c'] = E[c'], Z[2c'+1] = O[c'] is the pruned 32-point DFT over a
+    fft16(E);
+    fft16(O);
+    // step 2: Z[c] *= w512^(b c); step 3a: transpose through LDS
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        bufE[c * kXpStride + b] = cmul(E[c], tw[(2 * c) * 16 + b]);
+        bufO[c * kXpStride + b] = cmul(O[c], tw[(2 * c + 1) * 16 + b]);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int bb = 0; bb < 16; ++bb) {
+        E[bb] = bufE[b * kXpStride + bb];
+        O[bb] = bufO[b * kXpStride + bb];
+    }
+    wave_lds_sync();
+    // step 3b: 16-point FFT over b gives X[c + 32 d] for c = 2 b (E) and 2 b + 1 (O)
+    fft16(E);
+    fft16(O);
+#pragma unroll
+    for (int d = 0; d < 16; ++d) {
+        acc[0][d] = fmaf(E[d].x, E[d].x, fmaf(E[d].y, E[d].y, acc[0][d]));
+        acc[1][d] = fmaf(O[d].x, O[d].x, fmaf(O[d].y, O[d].y, acc[1][d]));
+    }
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void bf_fp32_kernel(LaunchArgs a)
+{
+    __shared__ __align__(16) float2 s_union[kUnionF2];
+    __shared__ __align__(16) float2 s_tw[32 * 16];
+
+    // Workgroups are dispatched round-robin over the 8 XCDs; the four s0
+    // workgroups of one channel-frame differ only in bits 3-4 of the id, so
+    // they share an XCD (and its L2) and read the raw block once from HBM.
+    const int x = blockIdx.x;
+    const int s0 = (x >> 3) & 3;
+    const int unit = ((x >> 5) << 3) | (x & 7);
+    if (unit >= a.n_units) return;
+    const int chan = unit % a.n_chan;
+    const int t = threadIdx.x;
+    const int g = t >> 4;      // group: s2 = g >> 2 (= wave), j = g & 3
+    const int b = t & 15;
+    const int s2 = g >> 2, j = g & 3;
+
+    for (int i = t; i < 32 * 16; i += kThreads) s_tw[i] = a.tw[i];
+    float2 W[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) W[c] = a.ew[((size_t)chan * kBeamEW + j) * kCyl + c];
+
+    const uint8_t* src = a.in + (size_t)unit * a.n_blk * (kUp * kInputs);
+    float4* T = reinterpret_cast<float4*>(s_union);
+    float2* bufE = s_union + g * 2 * kXpBuf;
+    float2* bufO = bufE + kXpBuf;
+
+    uint2 raw[16];
+#pragma unroll
+    for (int tau = 0; tau < 16; ++tau)
+        raw[tau] = *reinterpret_cast<const uint2*>(src + tau * kInputs + 8 * t);
+
+    float acc[2][16];
+#pragma unroll
+    for (int d = 0; d < 16; ++d) acc[0][d] = acc[1][d] = 0.f;
+
+    for (int blk = 0; blk < a.n_blk; ++blk) {
+        // A: time DFT of this thread's 8 inputs
+        switch (s0) {
+        case 0: time_dft<0>(raw, T, t); break;
+        case 1: time_dft<1>(raw, T, t); break;
+        case 2: time_dft<2>(raw, T, t); break;
+        default: time_dft<3>(raw, T, t); break;
+        }
+        __syncthreads();
+        // prefetch the next block's samples while the transforms run
+        if (blk + 1 < a.n_blk) {
+            const uint8_t* nxt = src + (size_t)(blk + 1) * (kUp * kInputs);
+#pragma unroll
+            for (int tau = 0; tau < 16; ++tau)
+                raw[tau] = *reinterpret_cast<const uint2*>(nxt + tau * kInputs + 8 * t);
+        }
+        // B1: E-W phasing while loading this group's two lines (feeds 16 a + b)
+        float2 v0[16], v1[16];
+#pragma unroll
+        for (int aa = 0; aa < 16; ++aa) {
+            float2 p0 = make_float2(0.f, 0.f), p1 = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float4 q = T[s2 * 1024 + c * 256 + 16 * aa + b];
+                p0 = cmac(p0, make_float2(q.x, q.y), W[c]);
+                p1 = cmac(p1, make_float2(q.z, q.w), W[c]);
+            }
+            v0[aa] = p0;
+            v1[aa] = p1;
+        }
+        __syncthreads();
+        // B2: N-S transform of both polarisations, power into per-bin accumulators
+        ns_line_power(v0, acc, bufE, bufO, s_tw, b);
+        ns_line_power(v1, acc, bufE, bufO, s_tw, b);
+        __syncthreads();
+    }
+
+    // per-bin powers -> LDS, then gather by the bin table into out[beam][q]
+    float* P = reinterpret_cast<float*>(s_union);
+#pragma unroll
+    for (int d = 0; d < 16; ++d) {
+        P[g * 512 + 2 * b + 32 * d] = acc[0][d];
+        P[g * 512 + 2 * b + 1 + 32 * d] = acc[1][d];
+    }
+    __syncthreads();
+    const int32_t* lut = a.lut + (size_t)chan * kBeamNS;
+    float* dst = a.out + (size_t)unit * kOutPerUnit;
+#pragma unroll 4
+    for (int it = 0; it < 16; ++it) {
+        const int u = it * kThreads + t;
+        const int beam = u >> 2, q2 = u & 3;
+        const int jj = beam >> 8, m = beam & 255;
+        const int ss2 = (q2 + 2) & 3;  // q = s0 + 4 q2 holds s = (q + 8) mod 16 = s0 + 4 ss2
+        const int k = lut[m];
+        dst[beam * kUp + s0 + 4 * q2] = P[(ss2 * 4 + jj) * 512 + k];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream)
+{
+    if (a.n_units <= 0) return hipSuccess;
+    const int groups8 = (a.n_units + 7) / 8;
+    dim3 grid(groups8 * 32), block(kThreads);
+    LaunchArgs args = a;
+    void* params[] = {&args};
+    return hipLaunchKernel(reinterpret_cast<const void*>(&bf_fp32_kernel), grid, block, params, 0,
+                           stream);
+}
+
+}  // namespace bf

@@ -1,0 +1,307 @@
+// Host side of libbeamform: argument validation, FP64 precompute of the
+// per-channel tables, plan lifetime and the C ABI entry points.
+//
+// Tables (all computed in FP64, rounded once to FP32):
+//   lut[chan][m]  Eq. (1)-(2) of the paper (Sec. 3.1): the FFT bin nearest
+//                 desired pointing m, floor(N P f d sin(theta_m) / c + 0.5)
+//                 reduced mod N P.  Eq. (2) is Eq. (1) at another frequency,
+//                 so the formula is evaluated per channel.
+//   ew[chan][j][c] E-W exact phasing (Sec. 3, Sec. 3.1):
+//                 exp(-2 pi i f x_c sin(phi_j) / c).
+//   tw[c][b]      Inter-stage twiddles of the 512-point N-S transform,
+//                 exp(-2 pi i ((b c) mod 512) / 512), c < 32, b < 16.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "bf_internal.h"
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+thread_local std::string g_init_error;
+
+int32_t fail(bf_plan* p, int32_t status, const std::string& msg)
+{
+    if (p) p->err = msg;
+    else g_init_error = msg;
+    return status;
+}
+
+int32_t hip_fail(bf_plan* p, hipError_t e, const char* what)
+{
+    return fail(p, BF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Checks the sizes the kernels are specialised for.
+int32_t check_config(const bf_config* c, std::string* msg)
+{
+    if (!c) { *msg = "cfg is NULL"; return BF_E_INVAL; }
+    if (c->n_time <= 0 || c->n_time % bf::kUp != 0) {
+        *msg = "n_time must be a positive multiple of 16";
+        return BF_E_INVAL;
+    }
+    if (c->n_time > (1 << 20)) { *msg = "n_time too large"; return BF_E_INVAL; }
+    if (c->n_cyl <= 0 || c->n_feed <= 0 || c->n_pol <= 0 || c->pad <= 0 ||
+        c->n_beam_ns <= 0 || c->n_beam_ew <= 0 || c->n_upchan <= 0) {
+        *msg = "sizes must be positive";
+        return BF_E_INVAL;
+    }
+    if (!(c->feed_spacing_m > 0.0) || !(c->c0 > 0.0)) {
+        *msg = "feed_spacing_m and c0 must be positive";
+        return BF_E_INVAL;
+    }
+    if (c->reserved != 0) { *msg = "reserved must be 0"; return BF_E_INVAL; }
+    if (c->precision != BF_FP32_FFT && c->precision != BF_FP16_MFMA) {
+        *msg = "unknown precision";
+        return BF_E_INVAL;
+    }
+    if (c->n_cyl != bf::kCyl || c->n_feed != bf::kFeed || c->n_pol != bf::kPol ||
+        c->pad != bf::kPad || c->n_beam_ns != bf::kBeamNS || c->n_beam_ew != bf::kBeamEW ||
+        c->n_upchan != bf::kUp) {
+        *msg = "kernels are built for 4 cylinders x 256 feeds x 2 pols, P = 2, "
+               "256 x 4 beams and a 16-point time DFT";
+        return BF_E_UNSUPPORTED;
+    }
+    if (c->precision == BF_FP16_MFMA) {
+        *msg = "BF_FP16_MFMA is not available in this build";
+        return BF_E_UNSUPPORTED;
+    }
+    return BF_OK;
+}
+
+double default_cyl_x(int c) { return (c - 1.5) * 20.0; }
+double default_sin_theta(int m) { return (m - 127.5) / 128.0; }
+double default_sin_phi(int j) { return std::sin((j - 1.5) * 0.4 * kTwoPi / 360.0); }
+
+// Eq. (1) of the paper evaluated in FP64, then floor and reduction mod N P.
+int32_t eq1_bin(const bf_config* c, double f_hz, double sin_theta)
+{
+    const int nb = c->n_feed * c->pad;
+    const double t = (double)c->n_feed * (double)c->pad * f_hz * (c->feed_spacing_m / c->c0) *
+                     sin_theta + 0.5;
+    long long k = (long long)std::floor(t);
+    long long r = k % nb;
+    if (r < 0) r += nb;
+    return (int32_t)r;
+}
+
+int32_t fill_lut(const bf_config* c, const double* freqs, int32_t n_chan, int32_t* out,
+                 std::string* msg)
+{
+    const int nb = c->n_feed * c->pad;
+    for (int32_t ch = 0; ch < n_chan; ++ch) {
+        const double f = freqs[ch];
+        if (!std::isfinite(f) || !(f > 0.0)) { *msg = "channel frequency must be > 0"; return BF_E_INVAL; }
+        for (int m = 0; m < c->n_beam_ns; ++m) {
+            int32_t k;
+            if (c->lut_override) {
+                k = c->lut_override[(size_t)ch * c->n_beam_ns + m];
+                if (k < 0 || k >= nb) { *msg = "lut_override entry out of [0, N P)"; return BF_E_INVAL; }
+            } else {
+                const double s = c->sin_theta_ns ? c->sin_theta_ns[m] : default_sin_theta(m);
+                if (!std::isfinite(s)) { *msg = "sin_theta_ns must be finite"; return BF_E_INVAL; }
+                k = eq1_bin(c, f, s);
+            }
+            out[(size_t)ch * c->n_beam_ns + m] = k;
+        }
+    }
+    return BF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t beamform_default_config(bf_config* cfg)
+{
+    if (!cfg) return BF_E_INVAL;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->n_cyl = bf::kCyl;
+    cfg->n_feed = bf::kFeed;
+    cfg->n_pol = bf::kPol;
+    cfg->pad = bf::kPad;
+    cfg->n_beam_ns = bf::kBeamNS;
+    cfg->n_beam_ew = bf::kBeamEW;
+    cfg->n_upchan = bf::kUp;
+    cfg->n_time = 384;
+    cfg->feed_spacing_m = 0.3048;
+    cfg->c0 = 299792458.0;
+    cfg->precision = BF_FP32_FFT;
+    return BF_OK;
+}
+
+int32_t beamform_compute_lut(const bf_config* cfg, const double* chan_freq_hz, int32_t n_chan,
+                             int32_t* out)
+{
+    std::string msg;
+    if (!cfg || !chan_freq_hz || !out || n_chan <= 0) return fail(nullptr, BF_E_INVAL, "bad arguments");
+    if (cfg->n_feed <= 0 || cfg->pad <= 0 || cfg->n_beam_ns <= 0 || !(cfg->c0 > 0.0) ||
+        !(cfg->feed_spacing_m > 0.0))
+        return fail(nullptr, BF_E_INVAL, "bad geometry");
+    int32_t r = fill_lut(cfg, chan_freq_hz, n_chan, out, &msg);
+    return r == BF_OK ? BF_OK : fail(nullptr, r, msg);
+}
+
+int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t n_chan,
+                      void* stream, bf_plan** out_plan)
+{
+    g_init_error.clear();
+    if (!out_plan) return fail(nullptr, BF_E_INVAL, "out_plan is NULL");
+    if (!chan_freq_hz || n_chan <= 0) return fail(nullptr, BF_E_INVAL, "need n_chan > 0 frequencies");
+    std::string msg;
+    int32_t st = check_config(cfg, &msg);
+    if (st != BF_OK) return fail(nullptr, st, msg);
+
+    bf_plan* p = new (std::nothrow) bf_plan();
+    if (!p) return fail(nullptr, BF_E_NOMEM, "host allocation failed");
+    p->cfg = *cfg;
+    p->n_chan = n_chan;
+    p->freqs.assign(chan_freq_hz, chan_freq_hz + n_chan);
+    p->cyl_x.resize(bf::kCyl);
+    p->sin_theta.resize(bf::kBeamNS);
+    p->sin_phi.resize(bf::kBeamEW);
+    for (int c = 0; c < bf::kCyl; ++c) p->cyl_x[c] = cfg->cyl_x_m ? cfg->cyl_x_m[c] : default_cyl_x(c);
+    for (int m = 0; m < bf::kBeamNS; ++m)
+        p->sin_theta[m] = cfg->sin_theta_ns ? cfg->sin_theta_ns[m] : default_sin_theta(m);
+    for (int j = 0; j < bf::kBeamEW; ++j)
+        p->sin_phi[j] = cfg->sin_phi_ew ? cfg->sin_phi_ew[j] : default_sin_phi(j);
+    for (double v : p->cyl_x) if (!std::isfinite(v)) { delete p; return fail(nullptr, BF_E_INVAL, "cyl_x_m must be finite"); }
+    for (double v : p->sin_phi) if (!std::isfinite(v)) { delete p; return fail(nullptr, BF_E_INVAL, "sin_phi_ew must be finite"); }
+
+    p->lut.resize((size_t)n_chan * bf::kBeamNS);
+    bf_config tmp = *cfg;
+    tmp.sin_theta_ns = p->sin_theta.data();
+    st = fill_lut(&tmp, chan_freq_hz, n_chan, p->lut.data(), &msg);
+    if (st != BF_OK) { delete p; return fail(nullptr, st, msg); }
+    p->cfg.cyl_x_m = nullptr;
+    p->cfg.sin_theta_ns = nullptr;
+    p->cfg.sin_phi_ew = nullptr;
+    p->cfg.lut_override = nullptr;
+
+    // E-W weights and N-S twiddles in FP64, rounded once.
+    std::vector<float2> ew((size_t)n_chan * bf::kBeamEW * bf::kCyl);
+    for (int32_t ch = 0; ch < n_chan; ++ch)
+        for (int j = 0; j < bf::kBeamEW; ++j)
+            for (int c = 0; c < bf::kCyl; ++c) {
+                const double a = kTwoPi * p->freqs[ch] * p->cyl_x[c] * p->sin_phi[j] / cfg->c0;
+                ew[((size_t)ch * bf::kBeamEW + j) * bf::kCyl + c] =
+                    make_float2((float)std::cos(a), (float)-std::sin(a));
+            }
+    std::vector<float2> tw(32 * 16);
+    for (int c = 0; c < 32; ++c)
+        for (int b = 0; b < 16; ++b) {
+            const int r = (b * c) % bf::kBins;
+            const double a = kTwoPi * (double)r / (double)bf::kBins;
+            tw[c * 16 + b] = make_float2((float)std::cos(a), (float)-std::sin(a));
+        }
+
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { int32_t r = hip_fail(nullptr, e, "hipGetDevice"); delete p; return r; }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t lut_b = p->lut.size() * sizeof(int32_t), ew_b = ew.size() * sizeof(float2),
+                 tw_b = tw.size() * sizeof(float2);
+    if ((e = hipMalloc(&p->d_lut, lut_b)) != hipSuccess ||
+        (e = hipMalloc(&p->d_ew, ew_b)) != hipSuccess ||
+        (e = hipMalloc(&p->d_tw, tw_b)) != hipSuccess) {
+        int32_t r = fail(nullptr, BF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        beamform_destroy(p);
+        return r;
+    }
+    if ((e = hipMemcpyAsync(p->d_lut, p->lut.data(), lut_b, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(p->d_ew, ew.data(), ew_b, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(p->d_tw, tw.data(), tw_b, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+        int32_t r = hip_fail(nullptr, e, "table upload");
+        beamform_destroy(p);
+        return r;
+    }
+    *out_plan = p;
+    return BF_OK;
+}
+
+int32_t beamform_frame(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float* d_out,
+                       void* stream)
+{
+    if (!p) return BF_E_INVAL;
+    p->err.clear();
+    if (n_frames < 0) return fail(p, BF_E_INVAL, "n_frames < 0");
+    if (n_frames == 0) return BF_OK;
+    if (!d_in || !d_out) return fail(p, BF_E_INVAL, "NULL device buffer");
+    if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 15))
+        return fail(p, BF_E_INVAL, "device buffers must be 16-byte aligned");
+    const long long units = (long long)n_frames * p->n_chan;
+    if (units > (1LL << 26)) return fail(p, BF_E_INVAL, "batch too large");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(p, e, "hipGetDevice");
+    if (dev != p->device) return fail(p, BF_E_STATE, "current device differs from the plan's device");
+
+    bf::LaunchArgs a;
+    a.in = d_in;
+    a.out = d_out;
+    a.lut = p->d_lut;
+    a.ew = p->d_ew;
+    a.tw = p->d_tw;
+    a.n_chan = p->n_chan;
+    a.n_units = (int32_t)units;
+    a.n_blk = p->cfg.n_time / bf::kUp;
+    e = bf::launch_fp32(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
+    return BF_OK;
+}
+
+int32_t beamform_get_lut(const bf_plan* p, int32_t* host_out)
+{
+    if (!p || !host_out) return BF_E_INVAL;
+    std::memcpy(host_out, p->lut.data(), p->lut.size() * sizeof(int32_t));
+    return BF_OK;
+}
+
+int32_t beamform_plan_info(const bf_plan* p, int32_t* n_chan, int32_t* n_time, int32_t* precision)
+{
+    if (!p) return BF_E_INVAL;
+    if (n_chan) *n_chan = p->n_chan;
+    if (n_time) *n_time = p->cfg.n_time;
+    if (precision) *precision = p->cfg.precision;
+    return BF_OK;
+}
+
+int32_t beamform_destroy(bf_plan* p)
+{
+    if (!p) return BF_OK;
+    int32_t st = BF_OK;
+    int prev = -1;
+    if (hipGetDevice(&prev) == hipSuccess && prev != p->device) (void)hipSetDevice(p->device);
+    if (hipDeviceSynchronize() != hipSuccess) st = BF_E_DEVICE;
+    if (p->d_lut) (void)hipFree(p->d_lut);
+    if (p->d_ew) (void)hipFree(p->d_ew);
+    if (p->d_tw) (void)hipFree(p->d_tw);
+    if (prev >= 0 && prev != p->device) (void)hipSetDevice(prev);
+    delete p;
+    return st;
+}
+
+const char* beamform_strerror(int32_t status)
+{
+    switch (status) {
+    case BF_OK: return "ok";
+    case BF_E_INVAL: return "invalid argument";
+    case BF_E_NOMEM: return "out of memory";
+    case BF_E_DEVICE: return "device error";
+    case BF_E_STATE: return "invalid state";
+    case BF_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char* beamform_last_error(const bf_plan* p)
+{
+    return p ? p->err.c_str() : g_init_error.c_str();
+}
+
+}  // extern "C"

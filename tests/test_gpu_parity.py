@@ -1,0 +1,171 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance for the FP32 FFT path: every output's relative power error
+|P - P_ref| / P_ref <= 1e-5 on noise-bearing inputs (noiseless special cases
+with exact nulls use the error relative to the frame's maximum instead).
+"""
+import numpy as np
+import pytest
+
+import synth
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+TOL_FP32 = 1e-5
+C0 = 299_792_458.0
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    torch.cuda.init()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bfm():
+    import paper_1702_04728_amd as bf
+    bf.load_library()
+    return bf
+
+
+def _run(torch_mod, bfm, raw, freqs, **kw):
+    print("gpu run: raw %s freqs %s %s" % (raw.shape, list(np.round(np.asarray(freqs) / 1e6, 3)),
+                                           {k: v for k, v in kw.items() if k != "lut_override"}),
+          flush=True)
+    b = bfm.Beamformer(freqs, n_time=raw.shape[2], **kw)
+    d = torch_mod.from_numpy(np.ascontiguousarray(raw)).cuda()
+    out = b.frame(d)
+    torch_mod.cuda.synchronize()
+    res = out.cpu().numpy().astype(np.float64)
+    b.close()
+    return res
+
+
+def _rel(got, ref):
+    return np.abs(got - ref) / ref
+
+
+def test_config0_parity_and_peak(torch_mod, bfm, oracle_mod):
+    c = synth.config0()
+    got = _run(torch_mod, bfm, c["raw"], c["freqs"])
+    ref = oracle_mod.beamform(oracle_mod.Geometry(), c["freqs"], c["raw"])
+    err = _rel(got, ref)
+    print("config0 max rel err %.3e  p99.9 %.3e" % (err.max(), np.quantile(err, 0.999)))
+    assert err.max() <= TOL_FP32
+    b, q = np.unravel_index(np.argmax(got[0, 0]), got[0, 0].shape)
+    assert (b, q) == (3 * 256 + 171, 8)
+
+
+@pytest.mark.parametrize("n_frames,n_chan,seed", [(1, 3, 31), (2, 5, 32), (3, 1, 33)])
+def test_ragged_batches_uniform_bytes(torch_mod, bfm, oracle_mod, n_frames, n_chan, seed):
+    """Every byte value (including -8) and channel counts that leave partial
+    groups of 8 channel-frames (tail workgroups)."""
+    raw = synth.uniform_bytes(seed, (n_frames, n_chan, 384, 2048))
+    freqs = synth.chan_freq_hz(np.random.default_rng(seed).integers(0, 1024, n_chan))
+    got = _run(torch_mod, bfm, raw, freqs)
+    ref = oracle_mod.beamform(oracle_mod.Geometry(), freqs, raw)
+    err = _rel(got, ref)
+    print("ragged %dx%d max rel err %.3e" % (n_frames, n_chan, err.max()))
+    assert err.max() <= TOL_FP32
+
+
+@pytest.mark.parametrize("n_time", [16, 48, 400])
+def test_other_frame_lengths(torch_mod, bfm, oracle_mod, n_time):
+    raw = synth.uniform_bytes(40 + n_time, (2, 2, n_time, 2048))
+    freqs = np.array([433.2e6, 777.7e6])
+    got = _run(torch_mod, bfm, raw, freqs)
+    ref = oracle_mod.beamform(oracle_mod.Geometry(n_time=n_time), freqs, raw)
+    assert _rel(got, ref).max() <= TOL_FP32
+
+
+def test_custom_geometry_parity(torch_mod, bfm, oracle_mod):
+    rng = np.random.default_rng(7)
+    st = np.sort(rng.uniform(-0.95, 0.95, 256))
+    sp = np.sin(np.deg2rad(rng.uniform(-1.2, 1.2, 4)))
+    cx = np.array([-31.0, -9.5, 10.25, 29.0])
+    raw = synth.noise_frames(8, 1, 2)
+    freqs = np.array([402.1e6, 799.6e6])
+    got = _run(torch_mod, bfm, raw, freqs, sin_theta_ns=st, sin_phi_ew=sp, cyl_x_m=cx)
+    g = oracle_mod.Geometry(sin_theta_ns=st, sin_phi_ew=sp, cyl_x_m=cx)
+    ref = oracle_mod.beamform(g, freqs, raw)
+    assert _rel(got, ref).max() <= TOL_FP32
+
+
+def test_energy_even_odd_bins_on_gpu(torch_mod, bfm, oracle_mod):
+    """Parseval through the whole path on the GPU: even-bin run + odd-bin run with
+    the scaled-unitary E-W directions sums to 16 * 4 * 512 * sum|x|^2."""
+    f = 600e6
+    sp = np.arange(4) * C0 / (4 * f * 20.0)
+    raw = synth.uniform_bytes(13, (1, 1, 384, 2048))
+    even = (2 * np.arange(256)).astype(np.int32)[None]
+    tot = (_run(torch_mod, bfm, raw, [f], sin_phi_ew=sp, lut_override=even).sum()
+           + _run(torch_mod, bfm, raw, [f], sin_phi_ew=sp, lut_override=even + 1).sum())
+    x = oracle_mod.decode(raw)
+    assert abs(tot / (16 * 4 * 512 * np.sum(np.abs(x) ** 2)) - 1) < 1e-6
+
+
+def test_invariants_duplicates_subsets_determinism(torch_mod, bfm):
+    """Beams clamped to the same bin are bitwise equal; channel subsets run alone
+    reproduce the full run bitwise; repeated runs are bitwise identical."""
+    freqs = np.array([450e6, 600e6, 750e6])
+    raw = synth.noise_frames(9, 2, 3)
+    full = _run(torch_mod, bfm, raw, freqs)
+    again = _run(torch_mod, bfm, raw, freqs)
+    np.testing.assert_array_equal(full, again)
+    lut = bfm.compute_lut(freqs)
+    for c in range(3):
+        k = lut[c]
+        for kk in np.unique(k):
+            ms = np.nonzero(k == kk)[0]
+            if len(ms) > 1:
+                for j in range(4):
+                    blk = full[:, c, j * 256 + ms]
+                    assert np.all(blk == blk[:, :1])
+        sub = _run(torch_mod, bfm, np.ascontiguousarray(raw[:, c:c + 1]), freqs[c:c + 1])
+        np.testing.assert_array_equal(sub[:, 0], full[:, c])
+    assert len(np.unique(lut[1])) < 256  # 600 MHz does alias
+
+
+def test_pol_swap_symmetry(torch_mod, bfm):
+    """Stokes I is symmetric in the two polarisations (same spatial weights)."""
+    raw = synth.noise_frames(10, 1, 2)
+    sw = raw.reshape(1, 2, 384, 1024, 2)[..., ::-1].reshape(raw.shape)
+    freqs = [500e6, 700e6]
+    a = _run(torch_mod, bfm, raw, freqs)
+    b = _run(torch_mod, bfm, np.ascontiguousarray(sw), freqs)
+    assert _rel(a, b).max() <= 1e-6
+
+
+def test_config1_full_size_sampled(torch_mod, bfm, oracle_mod):
+    """The benchmark workload at full size (4 channels x 128 frames, one launch):
+    sampled channel-frames against the oracle, every output finite and positive."""
+    c = synth.config1()
+    got = _run(torch_mod, bfm, c["raw"], c["freqs"])
+    assert np.all(np.isfinite(got)) and np.all(got > 0)
+    units = [(0, 0), (0, 3), (37, 1), (64, 2), (101, 0), (127, 3)]
+    ref = oracle_mod.beamform(oracle_mod.Geometry(), c["freqs"], c["raw"], units=units)
+    for u, (f, ch) in enumerate(units):
+        err = _rel(got[f, ch], ref[u])
+        assert err.max() <= TOL_FP32, (f, ch, err.max())
+
+
+def test_zero_frames_and_argument_errors(torch_mod, bfm):
+    b = bfm.Beamformer([600e6])
+    empty = torch_mod.empty((0, 1, 384, 2048), dtype=torch_mod.uint8, device="cuda")
+    out = b.frame(empty)
+    assert out.shape == (0, 1, 1024, 16)
+    with pytest.raises(ValueError):
+        b.frame(torch_mod.zeros((1, 2, 384, 2048), dtype=torch_mod.uint8, device="cuda"))
+    with pytest.raises(TypeError):
+        b.frame(torch_mod.zeros((1, 1, 384, 2048), dtype=torch_mod.int8, device="cuda"))
+    # misaligned device pointer is rejected by the library itself
+    base = torch_mod.zeros(384 * 2048 + 16, dtype=torch_mod.uint8, device="cuda")
+    o = torch_mod.empty((1, 1, 1024, 16), dtype=torch_mod.float32, device="cuda")
+    import ctypes
+    st = b.lib.beamform_frame(b._plan, ctypes.c_void_p(base.data_ptr() + 1), 1,
+                              ctypes.c_void_p(o.data_ptr()), None)
+    assert st == -1
+    b.close()
