@@ -31,12 +31,20 @@ BYTES_PER_UNIT = 384 * 2048 + 1024 * 16 * 4  # 851,968 algorithmic HBM bytes per
 # Conventional flop count per sample (5 N log2 N FFTs): N-S 8 x 512-point = 184,320,
 # E-W 1024 beams x 2 pols x 4 complex MACs = 65,536, 2048 16-point DFTs = 40,960,
 # detection 8,192.  Times 384 samples per channel-frame.
-FLOPS_PER_UNIT = {"fp32": 384 * (184_320 + 65_536 + 40_960 + 8_192)}
-PEAK = {"fp32": (157.3, "TFLOP/s")}     # MI355X FP32 vector peak (published)
+# The FP16-MFMA path's algorithmic matrix work: four-step N-S transform, per
+# line 16,384 complex MACs (stage 1: 32 x 16 x 16, stage 2: 32 x 16 x 16), 8 lines
+# per sample, 8 real flops per complex MAC.
+FLOPS_PER_UNIT = {"fp32": 384 * (184_320 + 65_536 + 40_960 + 8_192),
+                  "fp16": 384 * 8 * 16_384 * 8}
+PEAK = {"fp32": (157.3, "TFLOP/s", "alu"),    # MI355X FP32 vector peak (published)
+        "fp16": (2500.0, "TFLOP/s", "mfma")}  # MI355X dense FP16 matrix peak
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAME = {"fp32": "bf_fp32_kernel"}
-KERNEL_SOURCES = {"fp32": ["paper_1702_04728_amd/csrc/bf_fp32.hip",
-                           "paper_1702_04728_amd/csrc/bf_internal.h"]}
+KERNEL_NAME = {"fp32": "bf_fp32_kernel", "fp16": "bf_mfma_kernel"}
+DTYPE = {"fp32": "f32", "fp16": "f16 x f16 -> f32 (MFMA)"}
+PATH_NAME = {"fp32": "fp32_fft", "fp16": "fp16_mfma"}
+_COMMON = ["paper_1702_04728_amd/csrc/bf_device.h", "paper_1702_04728_amd/csrc/bf_internal.h"]
+KERNEL_SOURCES = {"fp32": ["paper_1702_04728_amd/csrc/bf_fp32.hip"] + _COMMON,
+                  "fp16": ["paper_1702_04728_amd/csrc/bf_mfma.hip"] + _COMMON}
 
 
 def log(*a):
@@ -98,13 +106,62 @@ def copy_probe(torch, mib: int, reps: int):
     log("copy probe: %d x %d MiB" % (reps, mib))
 
 
+def time_path(torch, bf, prec, raw, freqs, units, args):
+    """Warm up, then time args.steps launches of one path on the current stream."""
+    beam = bf.Beamformer(freqs, precision=prec)
+    n_frames = raw.shape[0]
+    out = torch.empty(beam.out_shape(n_frames), dtype=torch.float32, device=raw.device)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        beam.frame(raw, out)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for i in range(args.steps):
+        starts[i].record(stream)
+        beam.frame(raw, out)
+        ends[i].record(stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    per = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    ms_step = total_ms / args.steps
+    beam.close()
+    log("%s: timed %d steps: %.4f ms/step (events)" % (prec, args.steps, ms_step))
+    kern_s = float(np.mean(per)) * 1e-3
+    flops = FLOPS_PER_UNIT[prec] * units
+    peak, punit, bound = PEAK[prec]
+    achieved = flops / kern_s / 1e12
+    return {
+        "value": round(units / (ms_step * 1e-3) * FRAME_S, 2),
+        "ms_per_step": round(ms_step, 5),
+        "dtype": DTYPE[prec],
+        "roofline": {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
+                     "unit": punit, "frac": round(achieved / peak, 4),
+                     "traffic": traffic_from_profiles(prec, units),
+                     "kernel": KERNEL_NAME[prec], "flops_per_launch": flops},
+        "hbm": {"achieved_GBs": round(BYTES_PER_UNIT * units / kern_s / 1e9, 1),
+                "peak_GBs": HBM_PEAK_GBS,
+                "frac": round(BYTES_PER_UNIT * units / kern_s / 1e9 / HBM_PEAK_GBS, 4),
+                "bytes_per_launch": BYTES_PER_UNIT * units},
+        "input_GBs": round(raw.numel() / (ms_step * 1e-3) / 1e9, 1),
+        "step_ms_p50": round(float(np.percentile(per, 50)), 5),
+        "step_ms_p99": round(float(np.percentile(per, 99)), 5),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=128)
-    ap.add_argument("--precision", default="fp32", choices=["fp32"])
+    ap.add_argument("--precision", default="both", choices=["fp32", "fp16", "both"],
+                    help="path(s) to time; with both, value is the FP32 path's")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -134,81 +191,44 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     raw = torch.from_numpy(raw_np).to(dev)
-    beam = bf.Beamformer(freqs, precision=args.precision)
-    out = torch.empty(beam.out_shape(n_frames), dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        beam.frame(raw, out)
-    torch.cuda.synchronize()
-    log("warmup done")
-
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall0 = time.perf_counter()
-    ev0.record(stream)
-    for i in range(args.steps):
-        starts[i].record(stream)
-        beam.frame(raw, out)
-        ends[i].record(stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall0
-    total_ms = ev0.elapsed_time(ev1)
-    per = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
-    ms_step = total_ms / args.steps
-    log("timed %d steps: %.4f ms/step (events), wall %.3f s" % (args.steps, ms_step, wall))
-
+    paths = ["fp32", "fp16"] if args.precision == "both" else [args.precision]
+    results = {}
+    for prec in paths:
+        results[prec] = time_path(torch, bf, prec, raw, freqs, units, args)
     if args.copy_probe_mib:
         copy_probe(torch, args.copy_probe_mib, 3)
 
-    unit_per_s = units / (ms_step * 1e-3)
-    value = unit_per_s * FRAME_S
-    kern_s = float(np.mean(per)) * 1e-3
-    flops = FLOPS_PER_UNIT[args.precision] * units
-    peak, punit = PEAK[args.precision]
-    achieved = flops / kern_s / 1e12
-    traffic = traffic_from_profiles(args.precision, units)
+    head = results[paths[0]]
     res = {
         "metric": METRIC,
-        "value": round(value, 2),
+        "value": head["value"],
         "unit": "channels (real time)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPE[paths[0]],
         "data": "synthetic",
         "config": {"workload": "config1: 4 channels (450/550/650/750 MHz) x %d frames of 384 "
                                "samples x 2048 inputs, 4+4-bit noise + 8 point sources; "
                                "1024 beams x 16 sub-channels per channel-frame" % n_frames,
-                   "path": "fp32_fft", "channel_frames_per_step": units,
+                   "path": PATH_NAME[paths[0]], "channel_frames_per_step": units,
                    "input_bytes_per_step": int(raw_np.nbytes)},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": punit, "frac": round(achieved / peak, 4),
-                     "traffic": traffic, "kernel": KERNEL_NAME[args.precision],
-                     "flops_per_launch": flops},
-        "hbm": {"achieved_GBs": round(BYTES_PER_UNIT * units / kern_s / 1e9, 1),
-                "peak_GBs": HBM_PEAK_GBS,
-                "frac": round(BYTES_PER_UNIT * units / kern_s / 1e9 / HBM_PEAK_GBS, 4),
-                "bytes_per_launch": BYTES_PER_UNIT * units},
-        "input_GBs": round(raw_np.nbytes / (ms_step * 1e-3) / 1e9, 1),
-        "step_ms_p50": round(float(np.percentile(per, 50)), 5),
-        "step_ms_p99": round(float(np.percentile(per, 99)), 5),
-        "frames_per_step_per_channel": n_frames,
+        "roofline": head["roofline"],
+        "hbm": head["hbm"],
+        "input_GBs": head["input_GBs"],
+        "step_ms_p50": head["step_ms_p50"],
+        "step_ms_p99": head["step_ms_p99"],
+        "paths": {PATH_NAME[p]: results[p] for p in paths},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)...")
         res["cpu_baseline"] = cpu_baseline(raw_np, freqs, args.cpu_seconds)
     else:
         res["cpu_baseline"] = None
-    beam.close()
     print(json.dumps(res), flush=True)
 
 

@@ -1,0 +1,220 @@
+// Device code shared by the beamformer kernels: complex helpers, the
+// sub-channel-class time DFT that opens every kernel, and the end-of-frame
+// gather of per-bin powers into clamped beams.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bf_internal.h"
+
+namespace bf {
+namespace dev {
+
+constexpr int kThreads = 256;
+
+// cos / sin of 2 pi k / 32 for the first octant.
+constexpr float kC16_1 = 0.92387953251128675613f;  // cos(pi/8)
+constexpr float kS16_1 = 0.38268343236508977173f;  // sin(pi/8)
+constexpr float kR2 = 0.70710678118654752440f;     // cos(pi/4)
+constexpr float kC32_1 = 0.98078528040323044913f;  // cos(pi/16)
+constexpr float kS32_1 = 0.19509032201612826785f;  // sin(pi/16)
+constexpr float kC32_3 = 0.83146961230254523708f;  // cos(3pi/16)
+constexpr float kS32_3 = 0.55557023301960222474f;  // sin(3pi/16)
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 w)
+{
+    return make_float2(fmaf(a.x, w.x, -a.y * w.y), fmaf(a.x, w.y, a.y * w.x));
+}
+// acc + a * w, complex
+__device__ __forceinline__ float2 cmac(float2 acc, float2 a, float2 w)
+{
+    return make_float2(fmaf(a.x, w.x, fmaf(-a.y, w.y, acc.x)), fmaf(a.x, w.y, fmaf(a.y, w.x, acc.y)));
+}
+
+// Multiply by (-i)^K.
+template <int K>
+__device__ __forceinline__ float2 rot(float2 a)
+{
+    constexpr int k = ((K % 4) + 4) % 4;
+    if constexpr (k == 0) return a;
+    else if constexpr (k == 1) return make_float2(a.y, -a.x);
+    else if constexpr (k == 2) return make_float2(-a.x, -a.y);
+    else return make_float2(-a.y, a.x);
+}
+
+template <int K>
+__device__ __forceinline__ float2 cs32()
+{
+    static_assert(K >= 0 && K <= 8, "first octant only");
+    if constexpr (K == 0) return make_float2(1.f, 0.f);
+    else if constexpr (K == 1) return make_float2(kC32_1, kS32_1);
+    else if constexpr (K == 2) return make_float2(kC16_1, kS16_1);
+    else if constexpr (K == 3) return make_float2(kC32_3, kS32_3);
+    else if constexpr (K == 4) return make_float2(kR2, kR2);
+    else if constexpr (K == 5) return make_float2(kS32_3, kC32_3);
+    else if constexpr (K == 6) return make_float2(kS16_1, kC16_1);
+    else if constexpr (K == 7) return make_float2(kS32_1, kC32_1);
+    else return make_float2(0.f, 1.f);
+}
+
+// Multiply by w32^K = e^{-2 pi i K / 32}.
+template <int K>
+__device__ __forceinline__ float2 tw32(float2 a)
+{
+    constexpr int k = ((K % 32) + 32) % 32;
+    if constexpr (k % 8 == 0) return rot<k / 8>(a);
+    else if constexpr (k < 8) {
+        const float2 cs = cs32<k>();
+        return cmul(a, make_float2(cs.x, -cs.y));
+    } else {
+        return rot<k / 8>(tw32<k % 8>(a));  // w32^k = (-i)^(k/8) w32^(k%8)
+    }
+}
+
+template <int K>
+__device__ __forceinline__ float2 tw16(float2 a) { return tw32<2 * K>(a); }
+
+// In-place DFT-4: X_k = sum_n x_n (-i)^(n k).
+__device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d)
+{
+    const float2 t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), t3 = csub(b, d);
+    a = cadd(t0, t2);
+    c = csub(t0, t2);
+    b = cadd(t1, rot<1>(t3));
+    d = csub(t1, rot<1>(t3));
+}
+
+// Orders LDS traffic between the lanes of one wavefront.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Workgroup -> (channel-frame, sub-channel class s0).  Workgroups are
+// dispatched round-robin over the 8 XCDs; the four s0 workgroups of one
+// channel-frame differ only in bits 3-4 of the id, so they run on the same XCD
+// and read each raw block from HBM once, then from that XCD's L2.
+struct Work {
+    int unit, s0, chan;
+};
+__device__ __forceinline__ Work work_of_block(int n_chan)
+{
+    const int x = blockIdx.x;
+    Work w;
+    w.s0 = (x >> 3) & 3;
+    w.unit = ((x >> 5) << 3) | (x & 7);
+    w.chan = w.unit % n_chan;
+    return w;
+}
+inline dim3 grid_for(int n_units) { return dim3(((n_units + 7) / 8) * 32); }
+
+// One 16-sample block of this thread's 8 inputs (bytes 8t .. 8t+7 of each
+// sample): time-DFT bins s = S0 + 4 s2, s2 = 0..3, by a radix-4 split of the
+// 16-point DFT:
+//   y[t1] = sum_t2 x[t1 + 4 t2] (-i)^(t2 S0)        (4-point DFT over the stride)
+//   T[s2] = sum_t1 (y[t1] w16^(t1 S0)) (-i)^(t1 s2)
+// y is formed on the raw nibbles four inputs at a time (bytewise integer
+// sums in a 32-bit word, biased so no byte borrows), converted to float once.
+// Output: T[s2 * 1024 + slot], slot = cyl * 256 + feed, float4 = both pols.
+template <int S0>
+__device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restrict__ T, int t)
+{
+    // nibble planes: re[tau][w], im[tau][w] hold the 4 offset-binary nibbles
+    // (value + 8) of inputs 8t + 4w .. 8t + 4w + 3 as bytes
+    constexpr uint32_t kLo = 0x0f0f0f0fu;
+    constexpr uint32_t kBias = 0x20202020u;  // +32 per byte keeps differences >= 0
+    uint32_t yr[4][2], yi[4][2];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+#pragma unroll
+        for (int t1 = 0; t1 < 4; ++t1) {
+            uint32_t r[4], m[4];
+#pragma unroll
+            for (int t2 = 0; t2 < 4; ++t2) {
+                const uint32_t v = w ? raw[t1 + 4 * t2].y : raw[t1 + 4 * t2].x;
+                r[t2] = (v >> 4) & kLo;
+                m[t2] = v & kLo;
+            }
+            // x_k = x[t1 + 4k]; y = sum_k x_k (-i)^(k S0), each byte = value + 32
+            if constexpr (S0 == 0) {
+                yr[t1][w] = r[0] + r[1] + r[2] + r[3];  // = sum(value) + 32
+                yi[t1][w] = m[0] + m[1] + m[2] + m[3];
+            } else if constexpr (S0 == 1) {  // x0 - i x1 - x2 + i x3
+                yr[t1][w] = (r[0] + m[1] + kBias) - (r[2] + m[3]);
+                yi[t1][w] = (m[0] + r[3] + kBias) - (r[1] + m[2]);
+            } else if constexpr (S0 == 2) {  // x0 - x1 + x2 - x3
+                yr[t1][w] = (r[0] + r[2] + kBias) - (r[1] + r[3]);
+                yi[t1][w] = (m[0] + m[2] + kBias) - (m[1] + m[3]);
+            } else {  // x0 + i x1 - x2 - i x3
+                yr[t1][w] = (r[0] + m[3] + kBias) - (m[1] + r[2]);
+                yi[t1][w] = (m[0] + r[1] + kBias) - (m[2] + r[3]);
+            }
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        float2 o[2][4];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int e = 2 * h + p;  // input 8t + e: feed 4 (t % 64) + h, pol p
+            const int w = e >> 2, sh = 8 * (e & 3);
+            float2 y[4];
+#pragma unroll
+            for (int t1 = 0; t1 < 4; ++t1)
+                y[t1] = make_float2((float)((yr[t1][w] >> sh) & 0xffu) - 32.f,
+                                    (float)((yi[t1][w] >> sh) & 0xffu) - 32.f);
+            y[1] = tw16<S0>(y[1]);
+            y[2] = tw16<2 * S0>(y[2]);
+            y[3] = tw16<3 * S0>(y[3]);
+            dft4(y[0], y[1], y[2], y[3]);
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) o[p][s2] = y[s2];
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2)
+            T[s2 * 1024 + 4 * t + h] = make_float4(o[0][s2].x, o[0][s2].y, o[1][s2].x, o[1][s2].y);
+    }
+}
+
+__device__ __forceinline__ void time_dft_class(int s0, const uint2 (&raw)[16], float4* T, int t)
+{
+    switch (s0) {
+    case 0: time_dft<0>(raw, T, t); break;
+    case 1: time_dft<1>(raw, T, t); break;
+    case 2: time_dft<2>(raw, T, t); break;
+    default: time_dft<3>(raw, T, t); break;
+    }
+}
+
+// Raw samples of one 16-sample block: thread t reads bytes 8t .. 8t+7 of
+// each sample (64 lanes x 8 B contiguous per sample).
+__device__ __forceinline__ void load_block(const uint8_t* __restrict__ blk, uint2 (&raw)[16], int t)
+{
+#pragma unroll
+    for (int tau = 0; tau < 16; ++tau)
+        raw[tau] = *reinterpret_cast<const uint2*>(blk + tau * kInputs + 8 * t);
+}
+
+// End of frame: P[(s2 * 4 + j) * 512 + k] holds the integrated power of FFT
+// bin k for sub-channel s0 + 4 s2 and E-W beam j.  Beam (j, m) takes bin
+// lut[m] (Eq. (1)); sub-channel q holds time-DFT bin (q + 8) mod 16.
+__device__ __forceinline__ void write_beams(const float* __restrict__ P,
+                                            const int32_t* __restrict__ lut,
+                                            float* __restrict__ dst, int s0, int t)
+{
+#pragma unroll 4
+    for (int it = 0; it < 16; ++it) {
+        const int u = it * kThreads + t;
+        const int beam = u >> 2, q2 = u & 3;
+        const int jj = beam >> 8, m = beam & 255;
+        const int ss2 = (q2 + 2) & 3;  // q = s0 + 4 q2 holds s = s0 + 4 ss2
+        dst[beam * kUp + s0 + 4 * q2] = P[(ss2 * 4 + jj) * 512 + lut[m]];
+    }
+}
+
+}  // namespace dev
+}  // namespace bf

@@ -32,95 +32,19 @@
 // the bin table into out[beam][q].
 #include <hip/hip_runtime.h>
 
-#include "bf_internal.h"
+#include "bf_device.h"
 
 namespace bf {
 namespace {
 
-constexpr int kThreads = 256;
+using namespace dev;
+
 constexpr int kXpStride = 17;                    // padded row of a transpose buffer
 constexpr int kXpBuf = 16 * kXpStride;           // float2 per buffer
 constexpr int kUnionF2 = 16 * 2 * kXpBuf;        // 16 groups x {E, O} buffers (8704)
 constexpr int kTF4 = 4 * 1024;                   // time-DFT output: 4 s2 x 1024 float4
 static_assert(kUnionF2 * 8 >= kTF4 * 16, "union region must hold the time-DFT output");
 static_assert(kUnionF2 * 8 >= 16 * 512 * 4, "union region must hold the per-bin powers");
-
-// e^{-2 pi i k / 16} and e^{-2 pi i k / 32} constants.
-constexpr float kC16_1 = 0.92387953251128675613f;  // cos(pi/8)
-constexpr float kS16_1 = 0.38268343236508977173f;  // sin(pi/8)
-constexpr float kR2 = 0.70710678118654752440f;     // cos(pi/4)
-constexpr float kC32_1 = 0.98078528040323044913f;  // cos(pi/16)
-constexpr float kS32_1 = 0.19509032201612826785f;  // sin(pi/16)
-constexpr float kC32_3 = 0.83146961230254523708f;  // cos(3pi/16)
-constexpr float kS32_3 = 0.55557023301960222474f;  // sin(3pi/16)
-
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 w)
-{
-    return make_float2(fmaf(a.x, w.x, -a.y * w.y), fmaf(a.x, w.y, a.y * w.x));
-}
-// a * c + acc, complex
-__device__ __forceinline__ float2 cmac(float2 acc, float2 a, float2 w)
-{
-    return make_float2(fmaf(a.x, w.x, fmaf(-a.y, w.y, acc.x)), fmaf(a.x, w.y, fmaf(a.y, w.x, acc.y)));
-}
-
-// Multiply by (-i)^K.
-template <int K>
-__device__ __forceinline__ float2 rot(float2 a)
-{
-    constexpr int k = ((K % 4) + 4) % 4;
-    if constexpr (k == 0) return a;
-    else if constexpr (k == 1) return make_float2(a.y, -a.x);
-    else if constexpr (k == 2) return make_float2(-a.x, -a.y);
-    else return make_float2(-a.y, a.x);
-}
-
-// cos and sin of 2 pi k / 32 for k in [0, 8], by symmetry from the table above.
-template <int K>
-__device__ __forceinline__ float2 cs32()
-{
-    static_assert(K >= 0 && K <= 8, "first octant only");
-    if constexpr (K == 0) return make_float2(1.f, 0.f);
-    else if constexpr (K == 1) return make_float2(kC32_1, kS32_1);
-    else if constexpr (K == 2) return make_float2(kC16_1, kS16_1);
-    else if constexpr (K == 3) return make_float2(kC32_3, kS32_3);
-    else if constexpr (K == 4) return make_float2(kR2, kR2);
-    else if constexpr (K == 5) return make_float2(kS32_3, kC32_3);
-    else if constexpr (K == 6) return make_float2(kS16_1, kC16_1);
-    else if constexpr (K == 7) return make_float2(kS32_1, kC32_1);
-    else return make_float2(0.f, 1.f);
-}
-
-// Multiply by w32^K = e^{-2 pi i K / 32}.
-template <int K>
-__device__ __forceinline__ float2 tw32(float2 a)
-{
-    constexpr int k = ((K % 32) + 32) % 32;
-    if constexpr (k % 8 == 0) return rot<k / 8>(a);
-    else if constexpr (k < 8) {
-        const float2 cs = cs32<k>();
-        return cmul(a, make_float2(cs.x, -cs.y));
-    } else {
-        // w32^k = (-i)^(k/8) * w32^(k%8)
-        return rot<k / 8>(tw32<k % 8>(a));
-    }
-}
-
-// Multiply by w16^K.
-template <int K>
-__device__ __forceinline__ float2 tw16(float2 a) { return tw32<2 * K>(a); }
-
-// In-place DFT-4 of (a, b, c, d): X_k = sum_n x_n (-i)^(n k).
-__device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d)
-{
-    const float2 t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), t3 = csub(b, d);
-    a = cadd(t0, t2);
-    c = csub(t0, t2);
-    b = cadd(t1, rot<1>(t3));
-    d = csub(t1, rot<1>(t3));
-}
 
 // In-place 16-point FFT, natural order in and out: v[k] <- sum_a v[a] w16^(a k).
 // Radix 4 x 4: a = 4 a1 + a2, k = k1 + 4 k2.
@@ -148,54 +72,6 @@ __device__ __forceinline__ void fft16(float2 (&v)[16])
     t = v[6]; v[6] = v[9]; v[9] = t;
     t = v[7]; v[7] = v[13]; v[13] = t;
     t = v[11]; v[11] = v[14]; v[14] = t;
-}
-
-// Orders LDS traffic between the lanes of one wavefront.
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Phase A for sub-channel class S0: time-DFT bins s = S0 + 4 s2 of this
-// thread's 8 inputs over one 16-sample block.
-//   y[t1] = sum_t2 x[t1 + 4 t2] (-i)^(t2 S0)      (DFT-4 over the stride)
-//   T[s2] = sum_t1 (y[t1] w16^(t1 S0)) (-i)^(t1 s2)
-template <int S0>
-__device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restrict__ T, int t)
-{
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-        float2 o[2][4];
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int e = 2 * h + p;  // input 8 t + e: feed 4 (t % 64) + h, pol p
-            float2 x[16];
-#pragma unroll
-            for (int tau = 0; tau < 16; ++tau) {
-                const uint32_t w = (e < 4) ? raw[tau].x : raw[tau].y;
-                const uint32_t byte = (w >> (8 * (e & 3))) & 0xffu;
-                x[tau] = make_float2((float)(byte >> 4) - 8.f, (float)(byte & 15u) - 8.f);
-            }
-            float2 y[4];
-#pragma unroll
-            for (int t1 = 0; t1 < 4; ++t1) {
-                y[t1] = cadd(cadd(x[t1], rot<S0>(x[t1 + 4])),
-                             cadd(rot<2 * S0>(x[t1 + 8]), rot<3 * S0>(x[t1 + 12])));
-            }
-            y[1] = tw16<S0>(y[1]);
-            y[2] = tw16<2 * S0>(y[2]);
-            y[3] = tw16<3 * S0>(y[3]);
-            dft4(y[0], y[1], y[2], y[3]);
-#pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2) o[p][s2] = y[s2];
-        }
-        // slot (cyl * 256 + feed) holds both pols of one feed
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2)
-            T[s2 * 1024 + 4 * t + h] = make_float4(o[0][s2].x, o[0][s2].y, o[1][s2].x, o[1][s2].y);
-    }
 }
 
 // Zero-padded 512-point N-S transform of one line held as x[a] = line[16 a + b]
@@ -251,19 +127,14 @@ __device__ __forceinline__ void ns_line_power(const float2 (&x)[16], float (&acc
     }
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void bf_fp32_kernel(LaunchArgs a)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void bf_fp32_kernel(LaunchArgs a)
 {
     __shared__ __align__(16) float2 s_union[kUnionF2];
     __shared__ __align__(16) float2 s_tw[32 * 16];
 
-    // Workgroups are dispatched round-robin over the 8 XCDs; the four s0
-    // workgroups of one channel-frame differ only in bits 3-4 of the id, so
-    // they share an XCD (and its L2) and read the raw block once from HBM.
-    const int x = blockIdx.x;
-    const int s0 = (x >> 3) & 3;
-    const int unit = ((x >> 5) << 3) | (x & 7);
-    if (unit >= a.n_units) return;
-    const int chan = unit % a.n_chan;
+    const Work wk = work_of_block(a.n_chan);
+    if (wk.unit >= a.n_units) return;
     const int t = threadIdx.x;
     const int g = t >> 4;      // group: s2 = g >> 2 (= wave), j = g & 3
     const int b = t & 15;
@@ -272,17 +143,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     for (int i = t; i < 32 * 16; i += kThreads) s_tw[i] = a.tw[i];
     float2 W[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) W[c] = a.ew[((size_t)chan * kBeamEW + j) * kCyl + c];
+    for (int c = 0; c < 4; ++c) W[c] = a.ew[((size_t)wk.chan * kBeamEW + j) * kCyl + c];
 
-    const uint8_t* src = a.in + (size_t)unit * a.n_blk * (kUp * kInputs);
+    const uint8_t* src = a.in + (size_t)wk.unit * a.n_blk * (kUp * kInputs);
     float4* T = reinterpret_cast<float4*>(s_union);
     float2* bufE = s_union + g * 2 * kXpBuf;
     float2* bufO = bufE + kXpBuf;
 
     uint2 raw[16];
-#pragma unroll
-    for (int tau = 0; tau < 16; ++tau)
-        raw[tau] = *reinterpret_cast<const uint2*>(src + tau * kInputs + 8 * t);
+    load_block(src, raw, t);
 
     float acc[2][16];
 #pragma unroll
@@ -290,20 +159,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 
     for (int blk = 0; blk < a.n_blk; ++blk) {
         // A: time DFT of this thread's 8 inputs
-        switch (s0) {
-        case 0: time_dft<0>(raw, T, t); break;
-        case 1: time_dft<1>(raw, T, t); break;
-        case 2: time_dft<2>(raw, T, t); break;
-        default: time_dft<3>(raw, T, t); break;
-        }
+        time_dft_class(wk.s0, raw, T, t);
         __syncthreads();
         // prefetch the next block's samples while the transforms run
-        if (blk + 1 < a.n_blk) {
-            const uint8_t* nxt = src + (size_t)(blk + 1) * (kUp * kInputs);
-#pragma unroll
-            for (int tau = 0; tau < 16; ++tau)
-                raw[tau] = *reinterpret_cast<const uint2*>(nxt + tau * kInputs + 8 * t);
-        }
+        if (blk + 1 < a.n_blk) load_block(src + (size_t)(blk + 1) * (kUp * kInputs), raw, t);
         // B1: E-W phasing while loading this group's two lines (feeds 16 a + b)
         float2 v0[16], v1[16];
 #pragma unroll
@@ -333,17 +192,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
         P[g * 512 + 2 * b + 1 + 32 * d] = acc[1][d];
     }
     __syncthreads();
-    const int32_t* lut = a.lut + (size_t)chan * kBeamNS;
-    float* dst = a.out + (size_t)unit * kOutPerUnit;
-#pragma unroll 4
-    for (int it = 0; it < 16; ++it) {
-        const int u = it * kThreads + t;
-        const int beam = u >> 2, q2 = u & 3;
-        const int jj = beam >> 8, m = beam & 255;
-        const int ss2 = (q2 + 2) & 3;  // q = s0 + 4 q2 holds s = (q + 8) mod 16 = s0 + 4 ss2
-        const int k = lut[m];
-        dst[beam * kUp + s0 + 4 * q2] = P[(ss2 * 4 + jj) * 512 + k];
-    }
+    write_beams(P, a.lut + (size_t)wk.chan * kBeamNS, a.out + (size_t)wk.unit * kOutPerUnit, wk.s0, t);
 }
 
 }  // namespace
@@ -351,12 +200,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream)
 {
     if (a.n_units <= 0) return hipSuccess;
-    const int groups8 = (a.n_units + 7) / 8;
-    dim3 grid(groups8 * 32), block(kThreads);
     LaunchArgs args = a;
     void* params[] = {&args};
-    return hipLaunchKernel(reinterpret_cast<const void*>(&bf_fp32_kernel), grid, block, params, 0,
-                           stream);
+    return hipLaunchKernel(reinterpret_cast<const void*>(&bf_fp32_kernel), dev::grid_for(a.n_units),
+                           dim3(dev::kThreads), params, 0, stream);
 }
 
 }  // namespace bf

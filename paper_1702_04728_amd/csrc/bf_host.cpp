@@ -67,10 +67,6 @@ int32_t check_config(const bf_config* c, std::string* msg)
                "256 x 4 beams and a 16-point time DFT";
         return BF_E_UNSUPPORTED;
     }
-    if (c->precision == BF_FP16_MFMA) {
-        *msg = "BF_FP16_MFMA is not available in this build";
-        return BF_E_UNSUPPORTED;
-    }
     return BF_OK;
 }
 
@@ -114,6 +110,63 @@ int32_t fill_lut(const bf_config* c, const double* freqs, int32_t n_chan, int32_
 }
 
 }  // namespace
+
+namespace bf {
+
+// Stage-1 B fragments: lane (q, n) element i holds row K = 8q + i of the real
+// form of the DFT-32 block, K = (a = 4q + i/2, re/im = i%2), column
+// (c = n + 16 (tau & 1), re/im = tau >> 1); theta = 2 pi a c / 32.
+// Stage-2 A fragments: lane (q, m) element i holds row (d = m, re/im = mu),
+// K = (b = 4q + i/2, re/im = i%2); phi = 2 pi b d / 16.
+// Complex product (cos - i sin)(xr + i xi): re = cos xr + sin xi,
+// im = -sin xr + cos xi.  Each entry is FP64, split into FP16 hi + lo.
+void build_mfma_tables(void* host_buf)
+{
+    _Float16* h = static_cast<_Float16*>(host_buf);
+    auto put = [&](size_t frag, int lane, int i, double v) {
+        const _Float16 hi = (_Float16)v;
+        const _Float16 lo = (_Float16)(v - (double)hi);
+        h[((frag * 2 + 0) * 64 + lane) * 8 + i] = hi;
+        h[((frag * 2 + 1) * 64 + lane) * 8 + i] = lo;
+    };
+    for (int tau = 0; tau < 4; ++tau)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int i = 0; i < 8; ++i) {
+                const int q = lane >> 4, n = lane & 15;
+                const int a = 4 * q + i / 2, ri = i & 1, c = n + 16 * (tau & 1), ro = tau >> 1;
+                const double th = kTwoPi * (double)((a * c) % 32) / 32.0;
+                const double v = ro == 0 ? (ri == 0 ? std::cos(th) : std::sin(th))
+                                         : (ri == 0 ? -std::sin(th) : std::cos(th));
+                put(tau, lane, i, v);
+            }
+    _Float16* h2 = h + 8 * 64 * 8;
+    auto put2 = [&](int mu, int lane, int i, double v) {
+        const _Float16 hi = (_Float16)v;
+        const _Float16 lo = (_Float16)(v - (double)hi);
+        h2[((mu * 2 + 0) * 64 + lane) * 8 + i] = hi;
+        h2[((mu * 2 + 1) * 64 + lane) * 8 + i] = lo;
+    };
+    for (int mu = 0; mu < 2; ++mu)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int i = 0; i < 8; ++i) {
+                const int q = lane >> 4, d = lane & 15;
+                const int b = 4 * q + i / 2, ri = i & 1;
+                const double ph = kTwoPi * (double)((b * d) % 16) / 16.0;
+                const double v = mu == 0 ? (ri == 0 ? std::cos(ph) : std::sin(ph))
+                                         : (ri == 0 ? -std::sin(ph) : std::cos(ph));
+                put2(mu, lane, i, v);
+            }
+    float2* tw = reinterpret_cast<float2*>(h2 + 4 * 64 * 8);
+    for (int lane = 0; lane < 64; ++lane)
+        for (int e = 0; e < 8; ++e) {
+            const int q = lane >> 4, n = lane & 15;
+            const int c = n + 16 * (e >> 2), b = 4 * q + (e & 3);
+            const double a = kTwoPi * (double)((b * c) % kBins) / (double)kBins;
+            tw[lane * 8 + e] = make_float2((float)std::cos(a), (float)-std::sin(a));
+        }
+}
+
+}  // namespace bf
 
 extern "C" {
 
@@ -205,9 +258,12 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
     hipStream_t s = (hipStream_t)stream;
     const size_t lut_b = p->lut.size() * sizeof(int32_t), ew_b = ew.size() * sizeof(float2),
                  tw_b = tw.size() * sizeof(float2);
+    std::vector<unsigned char> mf(bf::kMfmaTableBytes);
+    bf::build_mfma_tables(mf.data());
     if ((e = hipMalloc(&p->d_lut, lut_b)) != hipSuccess ||
         (e = hipMalloc(&p->d_ew, ew_b)) != hipSuccess ||
-        (e = hipMalloc(&p->d_tw, tw_b)) != hipSuccess) {
+        (e = hipMalloc(&p->d_tw, tw_b)) != hipSuccess ||
+        (e = hipMalloc(&p->d_mf, mf.size())) != hipSuccess) {
         int32_t r = fail(nullptr, BF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
         beamform_destroy(p);
         return r;
@@ -215,6 +271,7 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
     if ((e = hipMemcpyAsync(p->d_lut, p->lut.data(), lut_b, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(p->d_ew, ew.data(), ew_b, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(p->d_tw, tw.data(), tw_b, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(p->d_mf, mf.data(), mf.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess) {
         int32_t r = hip_fail(nullptr, e, "table upload");
         beamform_destroy(p);
@@ -247,10 +304,12 @@ int32_t beamform_frame(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float*
     a.lut = p->d_lut;
     a.ew = p->d_ew;
     a.tw = p->d_tw;
+    a.mf = p->d_mf;
     a.n_chan = p->n_chan;
     a.n_units = (int32_t)units;
     a.n_blk = p->cfg.n_time / bf::kUp;
-    e = bf::launch_fp32(a, (hipStream_t)stream);
+    e = p->cfg.precision == BF_FP16_MFMA ? bf::launch_mfma(a, (hipStream_t)stream)
+                                         : bf::launch_fp32(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
     return BF_OK;
 }
@@ -281,6 +340,7 @@ int32_t beamform_destroy(bf_plan* p)
     if (p->d_lut) (void)hipFree(p->d_lut);
     if (p->d_ew) (void)hipFree(p->d_ew);
     if (p->d_tw) (void)hipFree(p->d_tw);
+    if (p->d_mf) (void)hipFree(p->d_mf);
     if (prev >= 0 && prev != p->device) (void)hipSetDevice(prev);
     delete p;
     return st;

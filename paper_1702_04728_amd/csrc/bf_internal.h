@@ -32,12 +32,21 @@ struct LaunchArgs {
     const int32_t* lut;    // [n_chan][256] kept bin per N-S beam
     const float2* ew;      // [n_chan][4][4] E-W weights W[j][c]
     const float2* tw;      // [32][16] N-S inter-stage twiddles w512^(b c)
+    const void* mf;        // matrix-core tables (FP16 path), layout below
     int32_t n_chan;
     int32_t n_units;       // n_frames * n_chan channel-frames
     int32_t n_blk;         // n_time / 16
 };
 
 hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream);
+hipError_t launch_mfma(const LaunchArgs& a, hipStream_t stream);
+
+// Matrix-core tables of the FP16 path, in per-lane fragment order:
+//   [8][64] x 8 halves  stage-1 DFT-32 block, tile tau in 0..3, hi then lo
+//   [4][64] x 8 halves  stage-2 DFT-16 block, tile mu in 0..1, hi then lo
+//   [64][8] float2      per-lane inter-stage twiddles w512^(b c)
+constexpr size_t kMfmaTableBytes = (8 * 64 + 4 * 64) * 16 + 64 * 8 * 8;
+void build_mfma_tables(void* host_buf);
 
 }  // namespace bf
 
@@ -50,5 +59,6 @@ struct bf_plan {
     int32_t* d_lut = nullptr;
     float2* d_ew = nullptr;
     float2* d_tw = nullptr;
+    void* d_mf = nullptr;
     std::string err;
 };
