@@ -115,6 +115,90 @@ int32_t beamform_init(const bf_config *cfg, const double *chan_freq_hz, int32_t 
 int32_t beamform_frame(bf_plan *plan, const uint8_t *d_in, int32_t n_frames, float *d_out,
                        void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Streaming (serving) loop.  Frames of 0.983 ms arrive for a varying set of
+ * channels (channels join and leave); each launch beamforms the active
+ * channels' newest chunk straight from a device input ring into a device
+ * output ring.  Per-bin partial integrations of a frame stay in HBM between
+ * chunks; a captured hipGraph is replayed per launch; frame latency is measured
+ * against each frame's availability time.  Paper Sec. 2 (one channel per GPU
+ * stream of 2.56 us samples), Sec. 3 (0.983 ms integration), Table 1.
+ * ------------------------------------------------------------------------- */
+
+#define BF_STREAM_JOIN 1
+#define BF_STREAM_LEAVE 2
+#define BF_STREAM_MAX_SLOTS 1024
+
+typedef struct {
+    int32_t frame;       /* applied before frame `frame` is processed */
+    int32_t op;          /* BF_STREAM_JOIN or BF_STREAM_LEAVE */
+    int32_t channel_id;  /* caller's channel identifier */
+    int32_t reserved;    /* must be 0 */
+    double freq_hz;      /* centre frequency (JOIN only) */
+} bf_stream_event;
+
+typedef struct {
+    const uint8_t *d_in_ring; /* device u8 [depth][max_slots][n_time][2048]: frame i of the
+                                 channel in slot s is read from entry (i mod depth, s) */
+    float *d_out_ring;        /* device f32 [depth][max_slots][1024][16]: result of frame i,
+                                 slot s, written to entry (i mod depth, s) */
+    int32_t depth;            /* ring entries (>= 1) */
+    int32_t max_slots;        /* channel slots, 1 .. BF_STREAM_MAX_SLOTS */
+    int32_t n_frames;         /* frames to run (>= 0) */
+    int32_t chunk;            /* samples per launch: a multiple of 16 dividing n_time
+                                 (0 = n_time, whole frames) */
+    int32_t pacing;           /* 0: launch as fast as possible; 1: real time, chunk c of
+                                 frame i becomes available at t0 + (i n_time + (c+1) chunk)
+                                 x 2.56 us */
+    int32_t use_graph;        /* 1: replay one captured hipGraph per launch; 0: plain launches */
+    int64_t mem_cap_bytes;    /* device bytes the stream may use for channel state and its
+                                 share of the rings (0: free memory at start); a JOIN that
+                                 would exceed it, or find no free slot, is rejected */
+    const bf_stream_event *events; /* host, sorted by frame; may be NULL if n_events = 0 */
+    int32_t n_events;
+    int32_t reserved;              /* must be 0 */
+    int32_t *slot_log;        /* optional host int32 [n_frames][max_slots]: channel id held
+                                 by each slot during each frame, -1 when empty */
+} bf_stream_desc;
+
+typedef struct {
+    int64_t frames;           /* frames run */
+    int64_t launches;         /* kernel launches (frames x chunks) */
+    int64_t channel_frames;   /* sum over frames of active channels */
+    int64_t late_frames;      /* frames whose latency exceeded n_time x 2.56 us */
+    int64_t joins, leaves, rejected_joins, ignored_events;
+    int32_t max_active, min_active;
+    double latency_p50_ms, latency_p99_ms, latency_max_ms, latency_mean_ms;
+    double service_mean_ms, service_p99_ms; /* device time of a frame's launches */
+    double wall_s;
+    double channels_realtime;  /* channel_frames / wall_s x n_time x 2.56 us */
+    double input_gb_s;         /* channel_frames x n_time x 2048 B / wall_s */
+    int64_t per_slot_bytes;    /* device bytes one active channel costs */
+    int32_t slot_capacity;     /* slots admissible under mem_cap_bytes */
+    int32_t reserved;
+} bf_stream_stats;
+
+/* Run the serving loop on the plan's geometry and precision (the plan's own
+ * channel list is not used; channels come from JOIN events).  Frame i:
+ * apply its events; (paced) wait for each chunk's availability; launch the
+ * beamformer for every active slot; the last chunk writes the frame's output.
+ * Latency of frame i = time its last launch completes - availability of its
+ * last chunk (host steady clock).  Blocks until all frames completed; `stream`
+ * is synchronised with before the first launch and after the last.  Library
+ * state (slot tables, partial accumulators, graph) is allocated at start and
+ * freed before returning.  Errors: BF_E_INVAL for a bad descriptor,
+ * BF_E_DEVICE for HIP failures. */
+int32_t beamform_stream(bf_plan *plan, const bf_stream_desc *desc, bf_stream_stats *stats,
+                        void *stream);
+
+/* The loop's host scheduler alone, without a device (test aid): applies the
+ * events frame by frame with the admission rule of beamform_stream, given the
+ * per-slot byte cost and the byte cap, and fills stats (joins, leaves,
+ * rejections, active counts, channel_frames) and desc->slot_log.  Launches
+ * nothing; desc device pointers are ignored. */
+int32_t beamform_stream_schedule(const bf_stream_desc *desc, int64_t per_slot_bytes,
+                                 int64_t cap_bytes, bf_stream_stats *stats);
+
 /* Copy the plan's bin table to host int32 [n_chan][n_beam_ns] (synchronous). */
 int32_t beamform_get_lut(const bf_plan *plan, int32_t *host_out);
 

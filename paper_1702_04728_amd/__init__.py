@@ -8,5 +8,6 @@ thin Python binding over it.
 """
 from .beamform import (  # noqa: F401
     BF_OK, EXPORTED, FP16_MFMA, FP32_FFT, LIB_PATH, N_BEAMS, N_INPUTS, N_UPCHAN,
-    Beamformer, BeamformError, compute_lut, load_library,
+    STREAM_JOIN, STREAM_LEAVE, STREAM_MAX_SLOTS, Beamformer, BeamformError, compute_lut,
+    load_library, stream_schedule,
 )

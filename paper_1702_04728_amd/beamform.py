@@ -27,9 +27,13 @@ N_BEAM_NS = 256
 # Every symbol include/beamform.h declares.
 EXPORTED = (
     "beamform_default_config", "beamform_compute_lut", "beamform_init", "beamform_frame",
-    "beamform_get_lut", "beamform_plan_info", "beamform_destroy", "beamform_strerror",
-    "beamform_last_error",
+    "beamform_stream", "beamform_stream_schedule", "beamform_get_lut", "beamform_plan_info",
+    "beamform_destroy", "beamform_strerror", "beamform_last_error",
 )
+
+STREAM_JOIN = 1
+STREAM_LEAVE = 2
+STREAM_MAX_SLOTS = 1024
 
 
 class BeamformError(RuntimeError):
@@ -52,6 +56,77 @@ class BfConfig(ctypes.Structure):
     ]
 
 
+class BfStreamEvent(ctypes.Structure):
+    _fields_ = [("frame", ctypes.c_int32), ("op", ctypes.c_int32),
+                ("channel_id", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("freq_hz", ctypes.c_double)]
+
+
+class BfStreamDesc(ctypes.Structure):
+    _fields_ = [("d_in_ring", ctypes.c_void_p), ("d_out_ring", ctypes.c_void_p),
+                ("depth", ctypes.c_int32), ("max_slots", ctypes.c_int32),
+                ("n_frames", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("pacing", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("mem_cap_bytes", ctypes.c_int64),
+                ("events", ctypes.POINTER(BfStreamEvent)), ("n_events", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("slot_log", ctypes.POINTER(ctypes.c_int32))]
+
+
+class BfStreamStats(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("channel_frames", ctypes.c_int64), ("late_frames", ctypes.c_int64),
+                ("joins", ctypes.c_int64), ("leaves", ctypes.c_int64),
+                ("rejected_joins", ctypes.c_int64), ("ignored_events", ctypes.c_int64),
+                ("max_active", ctypes.c_int32), ("min_active", ctypes.c_int32),
+                ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+                ("latency_max_ms", ctypes.c_double), ("latency_mean_ms", ctypes.c_double),
+                ("service_mean_ms", ctypes.c_double), ("service_p99_ms", ctypes.c_double),
+                ("wall_s", ctypes.c_double), ("channels_realtime", ctypes.c_double),
+                ("input_gb_s", ctypes.c_double), ("per_slot_bytes", ctypes.c_int64),
+                ("slot_capacity", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+def _events_array(events):
+    """events: iterable of (frame, op, channel_id, freq_hz), sorted by frame."""
+    ev = list(events)
+    arr = (BfStreamEvent * max(1, len(ev)))()
+    for i, (fr, op, cid, f) in enumerate(ev):
+        arr[i] = BfStreamEvent(int(fr), int(op), int(cid), 0, float(f))
+    return arr, len(ev)
+
+
+def _stream_desc(depth, max_slots, n_frames, chunk, pacing, use_graph, mem_cap_bytes, events,
+                 slot_log, d_in=None, d_out=None):
+    arr, n_ev = _events_array(events)
+    d = BfStreamDesc()
+    d.d_in_ring = d_in
+    d.d_out_ring = d_out
+    d.depth, d.max_slots, d.n_frames, d.chunk = int(depth), int(max_slots), int(n_frames), int(chunk)
+    d.pacing, d.use_graph, d.mem_cap_bytes = int(pacing), int(use_graph), int(mem_cap_bytes)
+    d.events = arr
+    d.n_events = n_ev
+    d.reserved = 0
+    if slot_log is not None:
+        d.slot_log = slot_log.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    return d, arr
+
+
+def stream_schedule(events, n_frames, max_slots, per_slot_bytes, cap_bytes, depth=1):
+    """Host-only dry run of the serving loop's scheduler: (stats dict, slot_log)."""
+    lib = load_library()
+    log = np.full((n_frames, max_slots), -1, dtype=np.int32)
+    d, keep = _stream_desc(depth, max_slots, n_frames, 0, 0, 0, 0, events, log)
+    st = BfStreamStats()
+    _check(lib.beamform_stream_schedule(ctypes.byref(d), int(per_slot_bytes), int(cap_bytes),
+                                        ctypes.byref(st)))
+    del keep
+    return st.as_dict(), log
+
+
 _lib = None
 
 
@@ -70,6 +145,10 @@ def load_library():
         "beamform_compute_lut": ([cp, vp, i32, vp], i32),
         "beamform_init": ([cp, vp, i32, vp, ctypes.POINTER(vp)], i32),
         "beamform_frame": ([vp, vp, i32, vp, vp], i32),
+        "beamform_stream": ([vp, ctypes.POINTER(BfStreamDesc), ctypes.POINTER(BfStreamStats), vp],
+                            i32),
+        "beamform_stream_schedule": ([ctypes.POINTER(BfStreamDesc), ctypes.c_int64,
+                                      ctypes.c_int64, ctypes.POINTER(BfStreamStats)], i32),
         "beamform_get_lut": ([vp, vp], i32),
         "beamform_plan_info": ([vp, vp, vp, vp], i32),
         "beamform_destroy": ([vp], i32),
@@ -207,6 +286,34 @@ class Beamformer:
                                      ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
         _check(st, self._plan)
         return out
+
+    def stream(self, in_ring, out_ring, events, n_frames, chunk=0, pacing=False, use_graph=True,
+               mem_cap_bytes=0, stream=None, log_slots=True):
+        """Run the serving loop (blocking).  in_ring: CUDA uint8 [depth][max_slots][n_time][2048];
+        out_ring: CUDA float32 [depth][max_slots][1024][16]; events: (frame, op, channel_id,
+        freq_hz) tuples sorted by frame.  Returns (stats dict, slot_log [n_frames][max_slots])."""
+        import torch
+        if not (isinstance(in_ring, torch.Tensor) and in_ring.is_cuda and in_ring.dtype == torch.uint8
+                and in_ring.is_contiguous() and in_ring.dim() == 4
+                and tuple(in_ring.shape[2:]) == (self.n_time, N_INPUTS)):
+            raise ValueError("in_ring must be a contiguous CUDA uint8 [depth][slots][%d][%d]"
+                             % (self.n_time, N_INPUTS))
+        depth, max_slots = int(in_ring.shape[0]), int(in_ring.shape[1])
+        if not (isinstance(out_ring, torch.Tensor) and out_ring.is_cuda
+                and out_ring.dtype == torch.float32 and out_ring.is_contiguous()
+                and tuple(out_ring.shape) == (depth, max_slots, N_BEAMS, N_UPCHAN)):
+            raise ValueError("out_ring must be a contiguous CUDA float32 [%d][%d][%d][%d]"
+                             % (depth, max_slots, N_BEAMS, N_UPCHAN))
+        log = np.full((n_frames, max_slots), -1, dtype=np.int32) if log_slots else None
+        d, keep = _stream_desc(depth, max_slots, n_frames, chunk, pacing, use_graph,
+                               mem_cap_bytes, events, log, ctypes.c_void_p(in_ring.data_ptr()),
+                               ctypes.c_void_p(out_ring.data_ptr()))
+        st = BfStreamStats()
+        rc = self.lib.beamform_stream(self._plan, ctypes.byref(d), ctypes.byref(st),
+                                      _stream_handle(stream))
+        del keep
+        _check(rc, self._plan)
+        return st.as_dict(), log
 
     def lut(self) -> np.ndarray:
         out = np.empty((self.n_chan, N_BEAM_NS), dtype=np.int32)

@@ -99,18 +99,62 @@ __device__ __forceinline__ void wave_lds_sync()
 // channel-frame differ only in bits 3-4 of the id, so they run on the same XCD
 // and read each raw block from HBM once, then from that XCD's L2.
 struct Work {
-    int unit, s0, chan;
+    int unit, s0;
 };
-__device__ __forceinline__ Work work_of_block(int n_chan)
+__device__ __forceinline__ Work work_of_block()
 {
     const int x = blockIdx.x;
     Work w;
     w.s0 = (x >> 3) & 3;
     w.unit = ((x >> 5) << 3) | (x & 7);
-    w.chan = w.unit % n_chan;
     return w;
 }
 inline dim3 grid_for(int n_units) { return dim3(((n_units + 7) / 8) * 32); }
+
+// Where one workgroup's channel-frame (or chunk of it) lives; see LaunchArgs.
+struct UnitIO {
+    const uint8_t* in;
+    float* out;
+    float* partial;  // this workgroup's partial sums (stream mode), else nullptr
+    int row;         // row of the bin table and E-W weights
+    bool first, last;
+};
+// False when the workgroup has no unit (uniform across the workgroup).
+__device__ __forceinline__ bool resolve_unit(const LaunchArgs& a, const Work& wk, UnitIO& io)
+{
+    if (a.st == nullptr) {
+        if (wk.unit >= a.n_units) return false;
+        io.in = a.in + (size_t)wk.unit * a.n_blk * (kUp * kInputs);
+        io.out = a.out + (size_t)wk.unit * kOutPerUnit;
+        io.partial = nullptr;
+        io.row = wk.unit % a.n_chan;
+        io.first = io.last = true;
+        return true;
+    }
+    if (wk.unit >= a.st->n_active) return false;
+    const int slot = a.st->slot[wk.unit];
+    const size_t entry = (size_t)a.st->ring_index * a.max_slots + slot;
+    const int chunk = a.st->chunk_index;
+    io.in = a.in + (entry * a.n_time + (size_t)chunk * a.n_blk * kUp) * kInputs;
+    io.out = a.out + entry * kOutPerUnit;
+    io.partial = a.partial + ((size_t)slot * 4 + wk.s0) * kPartialPerWg;
+    io.row = slot;
+    io.first = chunk == 0;
+    io.last = chunk == a.st->n_chunks - 1;
+    return true;
+}
+
+// Partial per-bin sums of a workgroup, element e of thread t at e * 256 + t.
+__device__ __forceinline__ void load_partial(float* acc, const float* __restrict__ p, int t)
+{
+#pragma unroll
+    for (int e = 0; e < kAccPerThread; ++e) acc[e] = p[e * kThreads + t];
+}
+__device__ __forceinline__ void store_partial(const float* acc, float* __restrict__ p, int t)
+{
+#pragma unroll
+    for (int e = 0; e < kAccPerThread; ++e) p[e * kThreads + t] = acc[e];
+}
 
 // One 16-sample block of this thread's 8 inputs (bytes 8t .. 8t+7 of each
 // sample): time-DFT bins s = S0 + 4 s2, s2 = 0..3, by a radix-4 split of the

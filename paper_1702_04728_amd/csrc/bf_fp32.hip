@@ -133,8 +133,9 @@ void bf_fp32_kernel(LaunchArgs a)
     __shared__ __align__(16) float2 s_union[kUnionF2];
     __shared__ __align__(16) float2 s_tw[32 * 16];
 
-    const Work wk = work_of_block(a.n_chan);
-    if (wk.unit >= a.n_units) return;
+    const Work wk = work_of_block();
+    UnitIO io;
+    if (!resolve_unit(a, wk, io)) return;
     const int t = threadIdx.x;
     const int g = t >> 4;      // group: s2 = g >> 2 (= wave), j = g & 3
     const int b = t & 15;
@@ -143,9 +144,9 @@ void bf_fp32_kernel(LaunchArgs a)
     for (int i = t; i < 32 * 16; i += kThreads) s_tw[i] = a.tw[i];
     float2 W[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) W[c] = a.ew[((size_t)wk.chan * kBeamEW + j) * kCyl + c];
+    for (int c = 0; c < 4; ++c) W[c] = a.ew[((size_t)io.row * kBeamEW + j) * kCyl + c];
 
-    const uint8_t* src = a.in + (size_t)wk.unit * a.n_blk * (kUp * kInputs);
+    const uint8_t* src = io.in;
     float4* T = reinterpret_cast<float4*>(s_union);
     float2* bufE = s_union + g * 2 * kXpBuf;
     float2* bufO = bufE + kXpBuf;
@@ -154,8 +155,13 @@ void bf_fp32_kernel(LaunchArgs a)
     load_block(src, raw, t);
 
     float acc[2][16];
+    static_assert(sizeof(acc) == kAccPerThread * sizeof(float), "partial-sum layout");
+    if (io.first) {
 #pragma unroll
-    for (int d = 0; d < 16; ++d) acc[0][d] = acc[1][d] = 0.f;
+        for (int d = 0; d < 16; ++d) acc[0][d] = acc[1][d] = 0.f;
+    } else {
+        load_partial(&acc[0][0], io.partial, t);
+    }
 
     for (int blk = 0; blk < a.n_blk; ++blk) {
         // A: time DFT of this thread's 8 inputs
@@ -184,6 +190,10 @@ void bf_fp32_kernel(LaunchArgs a)
         __syncthreads();
     }
 
+    if (!io.last) {  // frame continues in the next chunk's launch
+        store_partial(&acc[0][0], io.partial, t);
+        return;
+    }
     // per-bin powers -> LDS, then gather by the bin table into out[beam][q]
     float* P = reinterpret_cast<float*>(s_union);
 #pragma unroll
@@ -192,7 +202,7 @@ void bf_fp32_kernel(LaunchArgs a)
         P[g * 512 + 2 * b + 1 + 32 * d] = acc[1][d];
     }
     __syncthreads();
-    write_beams(P, a.lut + (size_t)wk.chan * kBeamNS, a.out + (size_t)wk.unit * kOutPerUnit, wk.s0, t);
+    write_beams(P, a.lut + (size_t)io.row * kBeamNS, io.out, wk.s0, t);
 }
 
 }  // namespace

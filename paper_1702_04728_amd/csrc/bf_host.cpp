@@ -298,7 +298,7 @@ int32_t beamform_frame(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float*
     if (e != hipSuccess) return hip_fail(p, e, "hipGetDevice");
     if (dev != p->device) return fail(p, BF_E_STATE, "current device differs from the plan's device");
 
-    bf::LaunchArgs a;
+    bf::LaunchArgs a{};
     a.in = d_in;
     a.out = d_out;
     a.lut = p->d_lut;
@@ -308,6 +308,9 @@ int32_t beamform_frame(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float*
     a.n_chan = p->n_chan;
     a.n_units = (int32_t)units;
     a.n_blk = p->cfg.n_time / bf::kUp;
+    a.n_time = p->cfg.n_time;
+    a.st = nullptr;
+    a.partial = nullptr;
     e = p->cfg.precision == BF_FP16_MFMA ? bf::launch_mfma(a, (hipStream_t)stream)
                                          : bf::launch_fp32(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(p, e, "kernel launch");

@@ -25,17 +25,41 @@ constexpr int kBeams = kBeamNS * kBeamEW;      // 1024
 constexpr int kUp = 16;                        // time-DFT length
 constexpr int kOutPerUnit = kBeams * kUp;      // floats per channel-frame
 
+constexpr int kAccPerThread = 32;              // per-bin power accumulators per thread
+constexpr int kPartialPerWg = 256 * kAccPerThread;  // floats of one workgroup's partial sums
+
+// Device state of one streaming launch (see beamform_stream).
+struct StreamState {
+    int32_t ring_index;    // ring entry of the frame this launch belongs to
+    int32_t chunk_index;   // chunk of the frame
+    int32_t n_chunks;      // chunks per frame
+    int32_t n_active;      // active slots; slot[0 .. n_active) are processed
+    int32_t slot[BF_STREAM_MAX_SLOTS];
+};
+constexpr size_t kStreamStateHeader = 4 * sizeof(int32_t);
+
 // Everything a kernel launch needs; device pointers only.
+//   batch mode (st == nullptr): unit u = frame * n_chan + chan reads
+//     in[u][n_blk * 16][2048], writes out[u][1024][16], tables row u % n_chan;
+//   stream mode: unit u < st->n_active is slot st->slot[u], ring entry
+//     e = st->ring_index * max_slots + slot; it reads samples
+//     [chunk_index * n_blk * 16, +n_blk * 16) of in[e][n_time][2048], tables
+//     row slot, keeps per-bin partial sums in partial[slot][4][kPartialPerWg]
+//     between chunks and writes out[e] at the frame's last chunk.
 struct LaunchArgs {
-    const uint8_t* in;     // [n_frames][n_chan][n_time][2048]
-    float* out;            // [n_frames][n_chan][1024][16]
-    const int32_t* lut;    // [n_chan][256] kept bin per N-S beam
-    const float2* ew;      // [n_chan][4][4] E-W weights W[j][c]
+    const uint8_t* in;
+    float* out;
+    const int32_t* lut;    // [rows][256] kept bin per N-S beam
+    const float2* ew;      // [rows][4][4] E-W weights W[j][c]
     const float2* tw;      // [32][16] N-S inter-stage twiddles w512^(b c)
     const void* mf;        // matrix-core tables (FP16 path), layout below
+    const StreamState* st; // stream mode state, or nullptr
+    float* partial;        // stream mode partial sums
     int32_t n_chan;
-    int32_t n_units;       // n_frames * n_chan channel-frames
-    int32_t n_blk;         // n_time / 16
+    int32_t n_units;       // batch mode: n_frames * n_chan; stream mode: max_slots
+    int32_t n_blk;         // 16-sample blocks per launch
+    int32_t n_time;        // stream mode: samples per frame (ring entry stride)
+    int32_t max_slots;     // stream mode: slots per ring entry
 };
 
 hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream);

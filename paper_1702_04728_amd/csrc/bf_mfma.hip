@@ -76,8 +76,9 @@ void bf_mfma_kernel(LaunchArgs a)
 {
     __shared__ __align__(16) float4 s_T[4 * 1024];  // time-DFT output, then per-bin powers
 
-    const Work wk = work_of_block(a.n_chan);
-    if (wk.unit >= a.n_units) return;
+    const Work wk = work_of_block();
+    UnitIO io;
+    if (!resolve_unit(a, wk, io)) return;
     const int t = threadIdx.x;
     const int lane = t & 63, s2 = t >> 6, q = lane >> 4, n = lane & 15;
 
@@ -103,19 +104,24 @@ void bf_mfma_kernel(LaunchArgs a)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) W[j][c] = a.ew[((size_t)wk.chan * kBeamEW + j) * kCyl + c];
+        for (int c = 0; c < 4; ++c) W[j][c] = a.ew[((size_t)io.row * kBeamEW + j) * kCyl + c];
 
-    const uint8_t* src = a.in + (size_t)wk.unit * a.n_blk * (kUp * kInputs);
+    const uint8_t* src = io.in;
     uint2 raw[16];
     load_block(src, raw, t);
 
     float acc[4][2][4];  // [E-W beam j][c = n + 16 nu][d = 4 q + i]
+    static_assert(sizeof(acc) == kAccPerThread * sizeof(float), "partial-sum layout");
+    if (io.first) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int nu = 0; nu < 2; ++nu)
+            for (int nu = 0; nu < 2; ++nu)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[j][nu][i] = 0.f;
+                for (int i = 0; i < 4; ++i) acc[j][nu][i] = 0.f;
+    } else {
+        load_partial(&acc[0][0][0], io.partial, t);
+    }
 
     for (int blk = 0; blk < a.n_blk; ++blk) {
         time_dft_class(wk.s0, raw, s_T, t);
@@ -185,6 +191,10 @@ void bf_mfma_kernel(LaunchArgs a)
             }
     }
 
+    if (!io.last) {  // frame continues in the next chunk's launch
+        store_partial(&acc[0][0][0], io.partial, t);
+        return;
+    }
     // per-bin powers -> LDS (bin k = c + 32 d), then gather into out[beam][q]
     float* P = reinterpret_cast<float*>(s_T);
 #pragma unroll
@@ -195,7 +205,7 @@ void bf_mfma_kernel(LaunchArgs a)
             for (int i = 0; i < 4; ++i)
                 P[(s2 * 4 + j) * 512 + n + 16 * nu + 32 * (4 * q + i)] = acc[j][nu][i];
     __syncthreads();
-    write_beams(P, a.lut + (size_t)wk.chan * kBeamNS, a.out + (size_t)wk.unit * kOutPerUnit, wk.s0, t);
+    write_beams(P, a.lut + (size_t)io.row * kBeamNS, io.out, wk.s0, t);
 }
 
 }  // namespace

@@ -1,0 +1,468 @@
+// Serving loop: frames for a varying set of channels, beamformed from a
+// device input ring into a device output ring, one launch per chunk of every
+// frame (paper Sec. 2: each frequency channel is an endless stream of 2.56 us
+// samples; Sec. 3 and Table 1: 0.983 ms output cadence).
+//
+// Host side per launch: apply the frame's join/leave events (slot assignment,
+// admission by memory), copy a small StreamState (ring entry, chunk, active
+// slots) host -> device, replay the captured kernel graph, record an event.
+// A completion thread waits on those events in order and timestamps them;
+// frame latency = completion of the frame's last launch - availability of its
+// last chunk.  All device state is allocated when the loop starts and freed
+// before it returns.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "bf_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+constexpr double kSampleS = 2.56e-6;
+constexpr int kInFlight = 8;  // launches the host may run ahead of the device
+constexpr size_t kTabBytes = bf::kBeamNS * sizeof(int32_t) + bf::kBeamEW * bf::kCyl * sizeof(float2);
+
+// Channel slots, admission and event application (pure host; no device).
+struct Scheduler {
+    int max_slots, capacity;
+    std::vector<int32_t> slot_chan;
+    std::vector<double> slot_freq;
+    int n_active = 0;
+    int64_t joins = 0, leaves = 0, rejected = 0, ignored = 0;
+
+    Scheduler(int max_slots_, int capacity_)
+        : max_slots(max_slots_), capacity(capacity_), slot_chan(max_slots_, -1),
+          slot_freq(max_slots_, 0.0) {}
+
+    int find(int32_t chan) const
+    {
+        for (int s = 0; s < max_slots; ++s)
+            if (slot_chan[s] == chan) return s;
+        return -1;
+    }
+    // Returns the slot a JOIN filled, else -1.
+    int apply(const bf_stream_event& e)
+    {
+        if (e.op == BF_STREAM_JOIN) {
+            if (e.channel_id < 0 || find(e.channel_id) >= 0 || !(e.freq_hz > 0.0) ||
+                !std::isfinite(e.freq_hz)) {
+                ++ignored;
+                return -1;
+            }
+            if (n_active >= capacity) {
+                ++rejected;
+                return -1;
+            }
+            for (int s = 0; s < max_slots; ++s)
+                if (slot_chan[s] < 0) {
+                    slot_chan[s] = e.channel_id;
+                    slot_freq[s] = e.freq_hz;
+                    ++n_active;
+                    ++joins;
+                    return s;
+                }
+            ++rejected;  // unreachable while capacity <= max_slots
+            return -1;
+        }
+        if (e.op == BF_STREAM_LEAVE) {
+            const int s = e.channel_id >= 0 ? find(e.channel_id) : -1;
+            if (s < 0) {
+                ++ignored;
+                return -1;
+            }
+            slot_chan[s] = -1;
+            --n_active;
+            ++leaves;
+            return -1;
+        }
+        ++ignored;
+        return -1;
+    }
+    int active(int32_t* slots) const
+    {
+        int n = 0;
+        for (int s = 0; s < max_slots; ++s)
+            if (slot_chan[s] >= 0) slots[n++] = s;
+        return n;
+    }
+};
+
+int32_t check_desc(const bf_stream_desc* d, std::string* msg)
+{
+    if (!d) { *msg = "desc is NULL"; return BF_E_INVAL; }
+    if (d->depth < 1) { *msg = "depth must be >= 1"; return BF_E_INVAL; }
+    if (d->max_slots < 1 || d->max_slots > BF_STREAM_MAX_SLOTS) {
+        *msg = "max_slots must be in [1, BF_STREAM_MAX_SLOTS]";
+        return BF_E_INVAL;
+    }
+    if (d->n_frames < 0) { *msg = "n_frames < 0"; return BF_E_INVAL; }
+    if (d->n_events < 0 || (d->n_events > 0 && !d->events)) { *msg = "bad events"; return BF_E_INVAL; }
+    if (d->reserved != 0) { *msg = "reserved must be 0"; return BF_E_INVAL; }
+    if (d->pacing != 0 && d->pacing != 1) { *msg = "pacing must be 0 or 1"; return BF_E_INVAL; }
+    if (d->mem_cap_bytes < 0) { *msg = "mem_cap_bytes < 0"; return BF_E_INVAL; }
+    for (int32_t i = 1; i < d->n_events; ++i)
+        if (d->events[i].frame < d->events[i - 1].frame) {
+            *msg = "events must be sorted by frame";
+            return BF_E_INVAL;
+        }
+    return BF_OK;
+}
+
+int64_t per_slot_bytes(int depth, int n_time)
+{
+    // the slot's share of both rings, its partial sums and its table rows
+    return (int64_t)depth * ((int64_t)n_time * bf::kInputs + (int64_t)bf::kOutPerUnit * 4) +
+           (int64_t)4 * bf::kPartialPerWg * 4 + (int64_t)kTabBytes;
+}
+
+double quantile(std::vector<double> v, double q)
+{
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    const double pos = q * (double)(v.size() - 1);
+    const size_t i = (size_t)pos;
+    const double f = pos - (double)i;
+    return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
+}
+
+// Bin table and E-W weights of one channel (FP64, rounded once), as in beamform_init.
+void channel_tables(const bf_plan* p, double f, unsigned char* dst)
+{
+    int32_t* lut = reinterpret_cast<int32_t*>(dst);
+    float2* ew = reinterpret_cast<float2*>(dst + bf::kBeamNS * sizeof(int32_t));
+    bf_config c = p->cfg;
+    c.sin_theta_ns = p->sin_theta.data();
+    c.lut_override = nullptr;
+    (void)beamform_compute_lut(&c, &f, 1, lut);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int j = 0; j < bf::kBeamEW; ++j)
+        for (int cy = 0; cy < bf::kCyl; ++cy) {
+            const double a = two_pi * f * p->cyl_x[cy] * p->sin_phi[j] / p->cfg.c0;
+            ew[j * bf::kCyl + cy] = make_float2((float)std::cos(a), (float)-std::sin(a));
+        }
+}
+
+struct LaunchRec {
+    int32_t frame;
+    bool last_chunk;
+    Clock::time_point avail;
+};
+
+}  // namespace
+
+extern "C" {
+
+int32_t beamform_stream_schedule(const bf_stream_desc* d, int64_t psb, int64_t cap,
+                                 bf_stream_stats* st)
+{
+    std::string msg;
+    if (check_desc(d, &msg) != BF_OK || psb <= 0 || cap < 0 || !st) return BF_E_INVAL;
+    std::memset(st, 0, sizeof(*st));
+    const int capacity = (int)std::min<int64_t>(d->max_slots, cap / psb);
+    Scheduler sch(d->max_slots, capacity);
+    int32_t ev = 0;
+    st->min_active = d->n_frames > 0 ? d->max_slots : 0;
+    for (int32_t i = 0; i < d->n_frames; ++i) {
+        while (ev < d->n_events && d->events[ev].frame <= i) sch.apply(d->events[ev++]);
+        if (d->slot_log)
+            std::memcpy(d->slot_log + (size_t)i * d->max_slots, sch.slot_chan.data(),
+                        sizeof(int32_t) * d->max_slots);
+        st->channel_frames += sch.n_active;
+        st->max_active = std::max(st->max_active, sch.n_active);
+        st->min_active = std::min(st->min_active, sch.n_active);
+    }
+    st->frames = d->n_frames;
+    st->joins = sch.joins;
+    st->leaves = sch.leaves;
+    st->rejected_joins = sch.rejected;
+    st->ignored_events = sch.ignored + (d->n_events - ev);
+    st->per_slot_bytes = psb;
+    st->slot_capacity = capacity;
+    return BF_OK;
+}
+
+int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st, void* stream)
+{
+    if (!p || !st) return BF_E_INVAL;
+    p->err.clear();
+    std::string msg;
+    int32_t rc = check_desc(d, &msg);
+    if (rc != BF_OK) { p->err = msg; return rc; }
+    const int n_time = p->cfg.n_time;
+    const int chunk = d->chunk ? d->chunk : n_time;
+    if (chunk <= 0 || chunk % bf::kUp != 0 || n_time % chunk != 0) {
+        p->err = "chunk must be a multiple of 16 dividing n_time";
+        return BF_E_INVAL;
+    }
+    if (d->n_frames > 0 && (!d->d_in_ring || !d->d_out_ring)) {
+        p->err = "NULL ring";
+        return BF_E_INVAL;
+    }
+    if (((uintptr_t)d->d_in_ring & 15) || ((uintptr_t)d->d_out_ring & 15)) {
+        p->err = "rings must be 16-byte aligned";
+        return BF_E_INVAL;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device) {
+        p->err = "current device differs from the plan's device";
+        return BF_E_STATE;
+    }
+    const int n_chunks = n_time / chunk;
+    std::memset(st, 0, sizeof(*st));
+    const int64_t psb = per_slot_bytes(d->depth, n_time);
+    int64_t cap = d->mem_cap_bytes;
+    if (cap == 0) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            p->err = "hipMemGetInfo failed";
+            return BF_E_DEVICE;
+        }
+        cap = (int64_t)free_b;
+    }
+    const int capacity = (int)std::min<int64_t>(d->max_slots, cap / psb);
+    st->per_slot_bytes = psb;
+    st->slot_capacity = capacity;
+
+    // ---- device and pinned state ----
+    hipError_t e = hipSuccess;
+    const int S = d->max_slots;
+    int32_t* d_lut = nullptr;
+    float2* d_ew = nullptr;
+    float* d_partial = nullptr;
+    bf::StreamState* d_state = nullptr;
+    bf::StreamState* h_state = nullptr;
+    unsigned char* h_tab = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t ev_start[kInFlight] = {}, ev_end[kInFlight] = {}, ev_sync = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    auto cleanup = [&]() {
+        if (s) (void)hipStreamSynchronize(s);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (int k = 0; k < kInFlight; ++k) {
+            if (ev_start[k]) (void)hipEventDestroy(ev_start[k]);
+            if (ev_end[k]) (void)hipEventDestroy(ev_end[k]);
+        }
+        if (ev_sync) (void)hipEventDestroy(ev_sync);
+        if (s) (void)hipStreamDestroy(s);
+        if (d_lut) (void)hipFree(d_lut);
+        if (d_ew) (void)hipFree(d_ew);
+        if (d_partial) (void)hipFree(d_partial);
+        if (d_state) (void)hipFree(d_state);
+        if (h_state) (void)hipHostFree(h_state);
+        if (h_tab) (void)hipHostFree(h_tab);
+    };
+    auto fail = [&](const char* what) -> int32_t {
+        p->err = std::string(what) + ": " + hipGetErrorString(e);
+        cleanup();
+        return BF_E_DEVICE;
+    };
+    if ((e = hipMalloc(&d_lut, (size_t)S * bf::kBeamNS * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&d_ew, (size_t)S * bf::kBeamEW * bf::kCyl * sizeof(float2))) != hipSuccess ||
+        (e = hipMalloc(&d_state, sizeof(bf::StreamState))) != hipSuccess)
+        return fail("hipMalloc");
+    if (n_chunks > 1 &&
+        (e = hipMalloc(&d_partial, (size_t)S * 4 * bf::kPartialPerWg * sizeof(float))) != hipSuccess)
+        return fail("hipMalloc partial sums");
+    if ((e = hipHostMalloc((void**)&h_state, sizeof(bf::StreamState) * kInFlight, 0)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&h_tab, kTabBytes * S, 0)) != hipSuccess)
+        return fail("hipHostMalloc");
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return fail("stream");
+    for (int k = 0; k < kInFlight; ++k)
+        if ((e = hipEventCreate(&ev_start[k])) != hipSuccess ||
+            (e = hipEventCreate(&ev_end[k])) != hipSuccess)
+            return fail("hipEventCreate");
+    if ((e = hipEventCreateWithFlags(&ev_sync, hipEventDisableTiming)) != hipSuccess) return fail("event");
+    // start after the caller's stream has reached this point
+    if ((e = hipEventRecord(ev_sync, (hipStream_t)stream)) != hipSuccess ||
+        (e = hipStreamWaitEvent(s, ev_sync, 0)) != hipSuccess)
+        return fail("stream ordering");
+
+    bf::LaunchArgs a{};
+    a.in = d->d_in_ring;
+    a.out = d->d_out_ring;
+    a.lut = d_lut;
+    a.ew = d_ew;
+    a.tw = p->d_tw;
+    a.mf = p->d_mf;
+    a.st = d_state;
+    a.partial = d_partial;
+    a.n_chan = 1;
+    a.n_units = S;
+    a.n_blk = chunk / bf::kUp;
+    a.n_time = n_time;
+    a.max_slots = S;
+    auto launch = [&](hipStream_t on) {
+        return p->cfg.precision == BF_FP16_MFMA ? bf::launch_mfma(a, on) : bf::launch_fp32(a, on);
+    };
+    if (d->use_graph) {
+        if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return fail("hipStreamBeginCapture");
+        hipError_t le = launch(s);
+        e = hipStreamEndCapture(s, &graph);
+        if (le != hipSuccess) { e = le; return fail("captured launch"); }
+        if (e != hipSuccess) return fail("hipStreamEndCapture");
+        if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess)
+            return fail("hipGraphInstantiate");
+    }
+
+    // ---- completion thread ----
+    std::vector<LaunchRec> recs(kInFlight);
+    std::vector<double> lat_ms((size_t)d->n_frames, 0.0), svc_ms((size_t)d->n_frames, 0.0);
+    std::atomic<int64_t> launched{0}, completed{0};
+    std::atomic<bool> stop{false};
+    std::atomic<int> thread_err{0};
+    const int device = p->device;
+    std::thread waiter([&]() {
+        (void)hipSetDevice(device);
+        for (int64_t L = 0;; ++L) {
+            while (L >= launched.load(std::memory_order_acquire)) {
+                if (stop.load(std::memory_order_acquire) && L >= launched.load()) return;
+                std::this_thread::yield();
+            }
+            const int k = (int)(L % kInFlight);
+            if (hipEventSynchronize(ev_end[k]) != hipSuccess) thread_err.store(1);
+            const Clock::time_point now = Clock::now();
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev_start[k], ev_end[k]);
+            const LaunchRec r = recs[k];
+            svc_ms[r.frame] += ms;
+            if (r.last_chunk)
+                lat_ms[r.frame] = std::chrono::duration<double, std::milli>(now - r.avail).count();
+            completed.store(L + 1, std::memory_order_release);
+        }
+    });
+    auto wait_completed = [&](int64_t n) {
+        while (completed.load(std::memory_order_acquire) < n && !thread_err.load())
+            std::this_thread::yield();
+    };
+
+    // ---- main loop ----
+    Scheduler sch(S, capacity);
+    std::vector<int64_t> tab_launch(S, -1);
+    std::vector<int32_t> act(S);
+    int32_t evi = 0;
+    int64_t L = 0;
+    st->min_active = d->n_frames > 0 ? S : 0;
+    const Clock::time_point t_start = Clock::now();
+    const Clock::time_point t0 = t_start + std::chrono::microseconds(500);
+    int32_t status = BF_OK;
+    for (int32_t i = 0; i < d->n_frames && status == BF_OK; ++i) {
+        while (evi < d->n_events && d->events[evi].frame <= i) {
+            const int slot = sch.apply(d->events[evi++]);
+            if (slot < 0) continue;
+            // the staging row may still feed an earlier copy: queued copies are
+            // read when they execute, so wait for it (drain the stream when that
+            // copy's launch has not even been issued, i.e. same-frame reuse)
+            if (tab_launch[slot] >= 0) {
+                if (tab_launch[slot] >= launched.load(std::memory_order_acquire)) {
+                    if ((e = hipStreamSynchronize(s)) != hipSuccess) { status = BF_E_DEVICE; break; }
+                } else {
+                    wait_completed(tab_launch[slot] + 1);
+                }
+            }
+            unsigned char* row = h_tab + kTabBytes * slot;
+            channel_tables(p, sch.slot_freq[slot], row);
+            if ((e = hipMemcpyAsync(d_lut + (size_t)slot * bf::kBeamNS, row,
+                                    bf::kBeamNS * sizeof(int32_t), hipMemcpyHostToDevice, s)) != hipSuccess ||
+                (e = hipMemcpyAsync(d_ew + (size_t)slot * bf::kBeamEW * bf::kCyl,
+                                    row + bf::kBeamNS * sizeof(int32_t),
+                                    bf::kBeamEW * bf::kCyl * sizeof(float2), hipMemcpyHostToDevice,
+                                    s)) != hipSuccess) {
+                status = BF_E_DEVICE;
+                break;
+            }
+            tab_launch[slot] = L;
+        }
+        if (status != BF_OK) break;
+        const int n_act = sch.active(act.data());
+        if (d->slot_log)
+            std::memcpy(d->slot_log + (size_t)i * S, sch.slot_chan.data(), sizeof(int32_t) * S);
+        st->channel_frames += n_act;
+        st->max_active = std::max(st->max_active, n_act);
+        st->min_active = std::min(st->min_active, n_act);
+        for (int c = 0; c < n_chunks; ++c, ++L) {
+            Clock::time_point avail =
+                t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(
+                         ((double)i * n_time + (double)(c + 1) * chunk) * kSampleS));
+            if (d->pacing) {
+                for (;;) {
+                    const auto now = Clock::now();
+                    if (now >= avail) break;
+                    if (avail - now > std::chrono::microseconds(300))
+                        std::this_thread::sleep_for(std::chrono::microseconds(100));
+                    else
+                        std::this_thread::yield();
+                }
+            }
+            wait_completed(L - kInFlight + 1);  // slot k of the state/event rings is free
+            if (thread_err.load()) { status = BF_E_DEVICE; break; }
+            if (!d->pacing) avail = Clock::now();
+            const int k = (int)(L % kInFlight);
+            bf::StreamState& hs = h_state[k];
+            hs.ring_index = i % d->depth;
+            hs.chunk_index = c;
+            hs.n_chunks = n_chunks;
+            hs.n_active = n_act;
+            std::memcpy(hs.slot, act.data(), sizeof(int32_t) * n_act);
+            recs[k] = LaunchRec{i, c == n_chunks - 1, avail};
+            if ((e = hipMemcpyAsync(d_state, &hs, bf::kStreamStateHeader + sizeof(int32_t) * n_act,
+                                    hipMemcpyHostToDevice, s)) != hipSuccess ||
+                (e = hipEventRecord(ev_start[k], s)) != hipSuccess ||
+                (e = (d->use_graph ? hipGraphLaunch(exec, s) : launch(s))) != hipSuccess ||
+                (e = hipEventRecord(ev_end[k], s)) != hipSuccess) {
+                status = BF_E_DEVICE;
+                break;
+            }
+            launched.store(L + 1, std::memory_order_release);
+        }
+    }
+    stop.store(true, std::memory_order_release);
+    waiter.join();
+    const Clock::time_point t_end = Clock::now();
+    if (status == BF_OK && thread_err.load()) {
+        status = BF_E_DEVICE;
+        e = hipErrorUnknown;
+    }
+    if (status != BF_OK) return fail("stream launch");
+    if ((e = hipEventRecord(ev_sync, s)) != hipSuccess ||
+        (e = hipStreamWaitEvent((hipStream_t)stream, ev_sync, 0)) != hipSuccess)
+        return fail("stream ordering");
+
+    // ---- statistics ----
+    const double budget_ms = n_time * kSampleS * 1e3;
+    st->frames = d->n_frames;
+    st->launches = L;
+    st->joins = sch.joins;
+    st->leaves = sch.leaves;
+    st->rejected_joins = sch.rejected;
+    st->ignored_events = sch.ignored + (d->n_events - evi);
+    for (double v : lat_ms) if (v > budget_ms) ++st->late_frames;
+    st->latency_p50_ms = quantile(lat_ms, 0.50);
+    st->latency_p99_ms = quantile(lat_ms, 0.99);
+    st->latency_max_ms = lat_ms.empty() ? 0.0 : *std::max_element(lat_ms.begin(), lat_ms.end());
+    double sum = 0.0, ssum = 0.0;
+    for (double v : lat_ms) sum += v;
+    for (double v : svc_ms) ssum += v;
+    st->latency_mean_ms = lat_ms.empty() ? 0.0 : sum / (double)lat_ms.size();
+    st->service_mean_ms = svc_ms.empty() ? 0.0 : ssum / (double)svc_ms.size();
+    st->service_p99_ms = quantile(svc_ms, 0.99);
+    st->wall_s = std::chrono::duration<double>(t_end - t_start).count();
+    if (st->wall_s > 0) {
+        st->channels_realtime = (double)st->channel_frames / st->wall_s * n_time * kSampleS;
+        st->input_gb_s = (double)st->channel_frames * n_time * bf::kInputs / st->wall_s / 1e9;
+    }
+    cleanup();
+    return BF_OK;
+}
+
+}  // extern "C"

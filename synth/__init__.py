@@ -169,3 +169,51 @@ def uniform_bytes(seed: int, shape) -> np.ndarray:
     """Every byte value equally likely, -8 included (exercises the full decode range)."""
     return np.random.Generator(np.random.PCG64(seed)).integers(0, 256, size=shape,
                                                               dtype=np.uint8)
+
+
+JOIN, LEAVE = 1, 2
+
+
+def churn_events(seed: int, n_frames: int, n_ids: int = 1024, initial: int = 64,
+                 rate_join: float = 0.02, rate_leave: float = 0.02, lo: int = 16, hi: int = 128):
+    """Seeded channel churn for the serving loop: frame 0 joins `initial` channel ids drawn
+    from [0, n_ids); then per frame Poisson(rate_join) joins and Poisson(rate_leave) leaves,
+    ids drawn uniformly from the inactive / active sets.  Events that would take the active
+    count outside [lo, hi] are counted in `clamped` and not emitted.
+    Returns (events [(frame, op, id, freq_hz)], clamped)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    active = set(int(c) for c in rng.choice(n_ids, size=initial, replace=False))
+    events = [(0, JOIN, c, float(chan_freq_hz(c))) for c in sorted(active)]
+    clamped = 0
+    for f in range(1, n_frames):
+        nj = int(rng.poisson(rate_join))
+        nl = int(rng.poisson(rate_leave))
+        for _ in range(nl):
+            if len(active) <= lo:
+                clamped += 1
+                continue
+            c = int(rng.choice(sorted(active)))
+            active.remove(c)
+            events.append((f, LEAVE, c, 0.0))
+        for _ in range(nj):
+            if len(active) >= hi:
+                clamped += 1
+                continue
+            free = sorted(set(range(n_ids)) - active)
+            c = int(rng.choice(free))
+            active.add(c)
+            events.append((f, JOIN, c, float(chan_freq_hz(c))))
+    return events, clamped
+
+
+def frame_pool(seed: int, n_distinct: int, sigma: float = SIGMA, freq_hz: float = 600e6,
+               n_sources: int = 2) -> np.ndarray:
+    """n_distinct seeded frames [n][384][2048] (noise plus a few point sources) used to fill
+    serving-loop input rings."""
+    ss = np.random.SeedSequence(seed)
+    a, b = ss.spawn(2)
+    srcs = random_sources(np.random.Generator(np.random.PCG64(a)), n_sources, 1.5)
+    out = np.empty((n_distinct, N_TIME, N_INPUTS), dtype=np.uint8)
+    channel_frames(np.random.Generator(np.random.PCG64(b)), freq_hz, n_distinct, srcs, out,
+                   sigma=sigma)
+    return out

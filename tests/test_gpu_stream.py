@@ -1,0 +1,144 @@
+"""GPU tests of the serving loop (beamform_stream): per-frame outputs equal the
+batch path bitwise and the oracle within tolerance, across channel churn;
+chunked ingest (partial integrations kept in HBM) equals whole-frame ingest
+bitwise; hipGraph replay equals plain launches bitwise; pacing and admission."""
+import numpy as np
+import pytest
+
+import synth
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+TOL = {"fp32": 1e-5, "fp16": 2e-3}
+J, L = 1, 2
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    torch.cuda.init()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bfm():
+    import paper_1702_04728_amd as bf
+    bf.load_library()
+    return bf
+
+
+@pytest.fixture(scope="module")
+def pool():
+    return synth.frame_pool(77, 7)
+
+
+def _ring(torch_mod, pool, depth, slots):
+    idx = np.array([(3 * k + s) % len(pool) for k in range(depth) for s in range(slots)])
+    dev = torch_mod.from_numpy(pool).cuda()
+    return dev[torch_mod.from_numpy(idx).cuda()].reshape(depth, slots, 384, 2048).contiguous()
+
+
+def _f(c):
+    return float(synth.chan_freq_hz(c))
+
+
+EVENTS = [(0, J, 100, _f(100)), (0, J, 700, _f(700)), (0, J, 300, _f(300)), (0, J, 901, _f(901)),
+          (3, L, 700, 0.0), (3, J, 512, _f(512)), (3, J, 44, _f(44)),
+          (6, L, 100, 0.0), (6, L, 901, 0.0), (6, J, 1000, _f(1000)),
+          (8, L, 44, 0.0), (8, J, 45, _f(45))]
+
+
+def _stream(torch_mod, bfm, ring, precision, n_frames=10, events=EVENTS, **kw):
+    depth, slots = ring.shape[0], ring.shape[1]
+    out = torch_mod.full((depth, slots, 1024, 16), -1.0, dtype=torch_mod.float32, device="cuda")
+    print("stream: precision %s ring %s frames %d %s" % (precision, tuple(ring.shape), n_frames, kw),
+          flush=True)
+    with bfm.Beamformer([600e6], precision=precision) as b:
+        st, log = b.stream(ring, out, events, n_frames, **kw)
+    torch_mod.cuda.synchronize()
+    return st, log, out.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_stream_outputs_match_batch_and_oracle(torch_mod, bfm, oracle_mod, pool, precision):
+    ring = _ring(torch_mod, pool, 4, 6)
+    st, log, out = _stream(torch_mod, bfm, ring, precision, use_graph=True)
+    assert st["frames"] == 10 and st["joins"] == 8 and st["leaves"] == 4
+    assert st["channel_frames"] == int((log >= 0).sum())
+    ring_np = ring.cpu().numpy()
+    checked = 0
+    for i in range(6, 10):                       # the ring keeps the last 4 frames
+        for s in np.nonzero(log[i] >= 0)[0]:
+            cid = int(log[i][s])
+            raw = ring_np[i % 4, s][None, None]
+            with bfm.Beamformer([_f(cid)], precision=precision) as b:
+                ref = b.frame(torch_mod.from_numpy(raw).cuda()).cpu().numpy()[0, 0]
+            np.testing.assert_array_equal(out[i % 4, s], ref)
+            checked += 1
+            if checked <= 3:
+                o = oracle_mod.beamform(oracle_mod.Geometry(), [_f(cid)], raw)[0, 0]
+                assert np.max(np.abs(out[i % 4, s] - o) / o) <= TOL[precision]
+    assert checked >= 10
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+@pytest.mark.parametrize("chunk", [128, 16])
+def test_chunked_partial_sums_equal_whole_frames(torch_mod, bfm, pool, precision, chunk):
+    ring = _ring(torch_mod, pool, 3, 5)
+    _, log_a, a = _stream(torch_mod, bfm, ring, precision, n_frames=7, chunk=0)
+    st, log_b, b = _stream(torch_mod, bfm, ring, precision, n_frames=7, chunk=chunk)
+    np.testing.assert_array_equal(log_a, log_b)
+    assert st["launches"] == 7 * (384 // chunk)
+    live = log_a[-1] >= 0
+    np.testing.assert_array_equal(a[:, live], b[:, live])
+
+
+def test_graph_replay_equals_plain_launches(torch_mod, bfm, pool):
+    ring = _ring(torch_mod, pool, 4, 6)
+    _, _, a = _stream(torch_mod, bfm, ring, "fp32", use_graph=True)
+    _, _, b = _stream(torch_mod, bfm, ring, "fp32", use_graph=False)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_paced_latency(torch_mod, bfm, pool):
+    ring = _ring(torch_mod, pool, 4, 8)
+    ev = [(0, J, c, _f(c)) for c in (10, 200, 400, 600, 800, 1000)]
+    st, _, _ = _stream(torch_mod, bfm, ring, "fp32", n_frames=300, events=ev, pacing=True)
+    print(st)
+    budget = 384 * 2.56e-3
+    assert st["frames"] == 300 and st["channel_frames"] == 1800
+    assert 0 < st["latency_p50_ms"] < budget
+    assert st["late_frames"] <= 30
+    # paced: wall time is at least the stream's own duration
+    assert st["wall_s"] >= 300 * budget * 1e-3
+    assert st["service_mean_ms"] > 0
+
+
+def test_admission_under_memory_cap(torch_mod, bfm, pool):
+    ring = _ring(torch_mod, pool, 2, 6)
+    ev = [(0, J, c, _f(c)) for c in (1, 2, 3, 4, 5)] + [(2, L, 2, 0.0), (2, J, 6, _f(6))]
+    with bfm.Beamformer([600e6]) as b:
+        out = torch_mod.zeros((2, 6, 1024, 16), dtype=torch_mod.float32, device="cuda")
+        st0, _ = b.stream(ring, out, [], 0)
+        psb = st0["per_slot_bytes"]
+        st, log = b.stream(ring, out, ev, 4, mem_cap_bytes=3 * psb)
+    dry, dry_log = bfm.stream_schedule(ev, 4, 6, psb, 3 * psb)
+    assert st["slot_capacity"] == 3 and st["rejected_joins"] == 2
+    np.testing.assert_array_equal(log, dry_log)
+    assert dry["rejected_joins"] == st["rejected_joins"]
+
+
+def test_stream_argument_errors(torch_mod, bfm, pool):
+    ring = _ring(torch_mod, pool, 2, 2)
+    out = torch_mod.zeros((2, 2, 1024, 16), dtype=torch_mod.float32, device="cuda")
+    with bfm.Beamformer([600e6]) as b:
+        with pytest.raises(bfm.BeamformError):
+            b.stream(ring, out, [], 3, chunk=100)
+        with pytest.raises(bfm.BeamformError):
+            b.stream(ring, out, [(2, J, 1, 5e8), (1, J, 2, 5e8)], 3)
+        with pytest.raises(ValueError):
+            b.stream(ring, out[:1], [], 3)
+        st, _ = b.stream(ring, out, [], 0)
+        assert st["frames"] == 0
