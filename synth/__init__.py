@@ -217,3 +217,94 @@ def frame_pool(seed: int, n_distinct: int, sigma: float = SIGMA, freq_hz: float 
     channel_frames(np.random.Generator(np.random.PCG64(b)), freq_hz, n_distinct, srcs, out,
                    sigma=sigma)
     return out
+
+
+# ---------------------------------------------------------------- config 4 sky
+DM_DELAY_S = 4.148808e-3   # cold-plasma dispersion delay constant, s GHz^2 / (pc cm^-3)
+
+
+def dispersion_delay_s(f_hz, dm: float) -> np.ndarray:
+    """Delay relative to infinite frequency: 4.148808 ms * DM * (f / GHz)^-2."""
+    return DM_DELAY_S * dm * (np.asarray(f_hz, dtype=np.float64) / 1e9) ** -2
+
+
+def sweep_c_idx(n_chan: int) -> np.ndarray:
+    """n_chan channels spread over the band: c_idx_i = floor((i + 1/2) * 1024 / n_chan)."""
+    return np.floor((np.arange(n_chan) + 0.5) * 1024 / n_chan).astype(np.int64)
+
+
+@dataclass
+class Config4Sky:
+    dm: float = 500.0
+    width_s: float = 1e-3
+    pulse_amp: float = 2.0          # per sub-channel component inside the pulse
+    pulse_sin_theta: float = 0.25
+    pulse_phi_deg: float = 0.2
+    t_arrive_800_s: float = 0.0     # arrival time at 800 MHz
+    rfi: tuple = ()                 # ((c_idx, sub-channel q, amplitude), ...)
+
+
+def config4_sky(seed: int, c_idx) -> Config4Sky:
+    """Seeded config-4 sky: the DM-500 1 ms pulse in one direction and 5 RFI tones at
+    seeded (channel, sub-channel) of the given channel set, amplitude 2."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c_idx = np.asarray(c_idx)
+    rfi = tuple((int(c_idx[rng.integers(0, len(c_idx))]), int(rng.integers(0, 16)), 2.0)
+                for _ in range(5))
+    return Config4Sky(pulse_sin_theta=float(rng.uniform(-0.5, 0.5)),
+                      pulse_phi_deg=float(rng.uniform(-0.5, 0.5)), rfi=rfi)
+
+
+def config4_frames(seed: int, c_idx, frames, sky: Config4Sky | None = None,
+                   sigma: float = SIGMA) -> np.ndarray:
+    """Bytes [len(frames)][len(c_idx)][384][2048]: noise + RFI tones (identical phase on
+    every input) + the dispersed pulse.  The pulse is built per 24.4 kHz sub-channel:
+    sub-channel q of channel f arrives at the cold-plasma delay of f + (q - 8) * 24.4 kHz
+    (relative to 800 MHz) and, inside its 1 ms width, carries a complex Gaussian amplitude
+    per 16-sample block placed on that sub-channel's frequency (an inverse 16-point DFT
+    of the block's sub-channel amplitudes)."""
+    c_idx = np.asarray(c_idx)
+    frames = np.asarray(frames)
+    sky = sky or config4_sky(seed, c_idx)
+    x, y = input_positions()
+    out = np.empty((len(frames), len(c_idx), N_TIME, N_INPUTS), dtype=np.uint8)
+    ss = np.random.SeedSequence(seed)
+    kids = ss.spawn(len(c_idx))
+    tau = np.arange(16)
+    q = np.arange(16)
+    nu = (q - 8) * SUBCHAN_HZ
+    for ci, c in enumerate(c_idx):
+        f = float(chan_freq_hz(c))
+        rng = np.random.Generator(np.random.PCG64(kids[ci]))
+        u = np.sin(np.deg2rad(sky.pulse_phi_deg))
+        v = np.cos(np.deg2rad(sky.pulse_phi_deg)) * sky.pulse_sin_theta
+        spat = np.exp(2j * np.pi * f * (x * u + y * v) / C0)
+        t_arr = sky.t_arrive_800_s + dispersion_delay_s(f + nu, sky.dm) - dispersion_delay_s(800e6, sky.dm)
+        tones = [(qq, a) for (cc, qq, a) in sky.rfi if cc == c]
+        for k, fr in enumerate(frames):
+            re = rng.standard_normal((N_TIME, N_INPUTS), dtype=np.float32) * sigma
+            im = rng.standard_normal((N_TIME, N_INPUTS), dtype=np.float32) * sigma
+            t_blk = (fr * N_TIME + 16 * np.arange(N_TIME // 16) + 8) * SAMPLE_DT   # block centres
+            inside = np.abs(t_blk[:, None] - t_arr[None, :]) <= sky.width_s / 2    # [blk][q]
+            if inside.any():
+                amp = (rng.standard_normal(inside.shape) + 1j * rng.standard_normal(inside.shape))
+                amp *= sky.pulse_amp / np.sqrt(2) * inside
+                # time samples of each block: sum_q amp[b, q] e^{+2 pi i nu_q t}
+                tt = (fr * N_TIME + np.arange(N_TIME)) * SAMPLE_DT
+                ph = np.exp(2j * np.pi * np.outer(tt, nu))                           # [t][q]
+                sig_t = (ph.reshape(N_TIME // 16, 16, 16) * amp[:, None, :]).sum(-1).reshape(-1)
+                sig = np.outer(sig_t, spat)
+                re += sig.real.astype(np.float32)
+                im += sig.imag.astype(np.float32)
+            for qq, a in tones:
+                tt = (fr * N_TIME + np.arange(N_TIME)) * SAMPLE_DT
+                s = a * np.exp(2j * np.pi * (qq - 8) * SUBCHAN_HZ * tt + 0.7j)
+                re += s.real.astype(np.float32)[:, None]
+                im += s.imag.astype(np.float32)[:, None]
+            np.rint(re, out=re)
+            np.rint(im, out=im)
+            np.clip(re, -7, 7, out=re)
+            np.clip(im, -7, 7, out=im)
+            out[k, ci] = encode(re, im)
+    _ = tau
+    return out

@@ -132,6 +132,23 @@ def test_coherent_rfi_parity(torch_mod, bfm, oracle_mod, precision):
     assert err.max() <= TOL[precision]
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_config4_sky_parity(torch_mod, bfm, oracle_mod, precision):
+    """Config-4 inputs (noise, dispersed DM-500 pulse, RFI tones in all inputs) for three
+    channels of the 64-channel sweep, over the frames where the pulse crosses them."""
+    c_idx = synth.sweep_c_idx(64)[[20, 31, 50]]
+    sky = synth.config4_sky(1004, c_idx)
+    f = synth.chan_freq_hz(c_idx)
+    arr = synth.dispersion_delay_s(f[1], 500) - synth.dispersion_delay_s(800e6, 500)
+    f0 = int(arr / (384 * 2.56e-6))
+    raw = synth.config4_frames(1004, c_idx, np.arange(f0 - 2, f0 + 2), sky=sky)
+    got = _run(torch_mod, bfm, raw, f, precision=precision)
+    ref = oracle_mod.beamform(oracle_mod.Geometry(), f, raw)
+    err = _rel(got, ref)
+    print("config4 %s max rel err %.3e" % (precision, err.max()))
+    assert err.max() <= TOL[precision]
+
+
 def test_energy_even_odd_bins_on_gpu(torch_mod, bfm, oracle_mod):
     """Parseval through the whole path on the GPU: even-bin run + odd-bin run with
     the scaled-unitary E-W directions sums to 16 * 4 * 512 * sum|x|^2."""

@@ -329,3 +329,32 @@ def test_alias_lands_where_geometry_says(oracle_mod):
     f_edge = C0 / (D * (1 + st))
     ang = [math.degrees(math.asin(max(-1.0, st - C0 / (ff * D)))) for ff in (f_edge, 800e6)]
     assert abs(ang[0] - lo) < 3 and abs(ang[1] - hi) < 3
+
+
+def test_dispersed_pulse_sweeps_down_in_subchannel(oracle_mod):
+    """Sec. 3.2: dispersion delays lower frequencies, 4.148808 ms DM (f/GHz)^-2.  Inside one
+    600 MHz channel a DM-500 pulse crosses the 16 sub-channels from the top (q = 15) to
+    the bottom (q = 0) in about 7 ms; the oracle's sub-channel order must show that."""
+    f = float(synth.chan_freq_hz(512))
+    sky = synth.Config4Sky(rfi=(), pulse_sin_theta=0.3, pulse_phi_deg=0.0, pulse_amp=3.0)
+    nu = (np.arange(16) - 8) * synth.SUBCHAN_HZ
+    arr = synth.dispersion_delay_s(f + nu, 500) - synth.dispersion_delay_s(800e6, 500)
+    frame_s = 384 * 2.56e-6
+    # q = 0 .. 15 spans 15 sub-channel spacings: d/df of the delay law times 15 x 24.4 kHz
+    slope = 2 * synth.DM_DELAY_S * 500 * (15 * synth.SUBCHAN_HZ / 1e9) / (f / 1e9) ** 3
+    assert abs((arr[0] - arr[15]) / slope - 1) < 0.02
+    f0 = int(arr[15] / frame_s)
+    frames = np.arange(f0, f0 + 9)
+    raw = synth.config4_frames(5, [512], frames, sky=sky)
+    out = oracle_mod.beamform(oracle_mod.Geometry(), [f], raw)   # [frame][1][beam][q]
+    per_q = out[:, 0].sum(axis=1)
+    base = np.median(per_q)
+    qs = [int(np.argmax(per_q[k])) for k in range(len(frames)) if per_q[k].max() > 1.5 * base]
+    assert len(qs) >= 6
+    assert all(a >= b for a, b in zip(qs, qs[1:]))        # moves down in frequency
+    assert qs[0] >= 13 and qs[-1] <= 2
+    # and it is seen in the beam of its direction
+    k = len(frames) // 2
+    beam = int(np.argmax(out[k, 0].sum(axis=1)))
+    g = oracle_mod.Geometry()
+    assert abs(g.sin_theta_ns[beam % 256] - 0.3) < 3 / 128
