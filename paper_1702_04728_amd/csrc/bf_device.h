@@ -145,15 +145,19 @@ __device__ __forceinline__ bool resolve_unit(const LaunchArgs& a, const Work& wk
 }
 
 // Partial per-bin sums of a workgroup, element e of thread t at e * 256 + t.
+template <int N>
 __device__ __forceinline__ void load_partial(float* acc, const float* __restrict__ p, int t)
 {
+    static_assert(N <= kAccPerThreadMax, "partial-sum slot too small");
 #pragma unroll
-    for (int e = 0; e < kAccPerThread; ++e) acc[e] = p[e * kThreads + t];
+    for (int e = 0; e < N; ++e) acc[e] = p[e * kThreads + t];
 }
+template <int N>
 __device__ __forceinline__ void store_partial(const float* acc, float* __restrict__ p, int t)
 {
+    static_assert(N <= kAccPerThreadMax, "partial-sum slot too small");
 #pragma unroll
-    for (int e = 0; e < kAccPerThread; ++e) p[e * kThreads + t] = acc[e];
+    for (int e = 0; e < N; ++e) p[e * kThreads + t] = acc[e];
 }
 
 // One 16-sample block of this thread's 8 inputs (bytes 8t .. 8t+7 of each
@@ -163,8 +167,10 @@ __device__ __forceinline__ void store_partial(const float* acc, float* __restric
 //   T[s2] = sum_t1 (y[t1] w16^(t1 S0)) (-i)^(t1 s2)
 // y is formed on the raw nibbles four inputs at a time (bytewise integer
 // sums in a 32-bit word, biased so no byte borrows), converted to float once.
-// Output: T[s2 * 1024 + slot], slot = cyl * 256 + feed, float4 = both pols.
-template <int S0>
+// Output (kPolPlanes = false): T[s2 * 1024 + slot] float4 = both pols of
+// slot = cyl * 256 + feed; (kPolPlanes = true): float2 planes
+// T[(s2 * 2 + pol) * 1024 + slot].
+template <int S0, bool kPolPlanes>
 __device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restrict__ T, int t)
 {
     // nibble planes: re[tau][w], im[tau][w] hold the 4 offset-binary nibbles
@@ -218,19 +224,28 @@ __device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restr
 #pragma unroll
             for (int s2 = 0; s2 < 4; ++s2) o[p][s2] = y[s2];
         }
+        if constexpr (kPolPlanes) {
+            float2* T2 = reinterpret_cast<float2*>(T);
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2)
-            T[s2 * 1024 + 4 * t + h] = make_float4(o[0][s2].x, o[0][s2].y, o[1][s2].x, o[1][s2].y);
+            for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+                for (int p = 0; p < 2; ++p) T2[(s2 * 2 + p) * 1024 + 4 * t + h] = o[p][s2];
+        } else {
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2)
+                T[s2 * 1024 + 4 * t + h] = make_float4(o[0][s2].x, o[0][s2].y, o[1][s2].x, o[1][s2].y);
+        }
     }
 }
 
+template <bool kPolPlanes>
 __device__ __forceinline__ void time_dft_class(int s0, const uint2 (&raw)[16], float4* T, int t)
 {
     switch (s0) {
-    case 0: time_dft<0>(raw, T, t); break;
-    case 1: time_dft<1>(raw, T, t); break;
-    case 2: time_dft<2>(raw, T, t); break;
-    default: time_dft<3>(raw, T, t); break;
+    case 0: time_dft<0, kPolPlanes>(raw, T, t); break;
+    case 1: time_dft<1, kPolPlanes>(raw, T, t); break;
+    case 2: time_dft<2, kPolPlanes>(raw, T, t); break;
+    default: time_dft<3, kPolPlanes>(raw, T, t); break;
     }
 }
 
@@ -243,10 +258,12 @@ __device__ __forceinline__ void load_block(const uint8_t* __restrict__ blk, uint
         raw[tau] = *reinterpret_cast<const uint2*>(blk + tau * kInputs + 8 * t);
 }
 
-// End of frame: P[(s2 * 4 + j) * 512 + k] holds the integrated power of FFT
+// End of frame: P[(s2 * 4 + j) * 512 + k] (plus P2[...] when the two
+// polarisations were integrated separately) holds the integrated power of FFT
 // bin k for sub-channel s0 + 4 s2 and E-W beam j.  Beam (j, m) takes bin
 // lut[m] (Eq. (1)); sub-channel q holds time-DFT bin (q + 8) mod 16.
 __device__ __forceinline__ void write_beams(const float* __restrict__ P,
+                                            const float* __restrict__ P2,
                                             const int32_t* __restrict__ lut,
                                             float* __restrict__ dst, int s0, int t)
 {
@@ -256,7 +273,8 @@ __device__ __forceinline__ void write_beams(const float* __restrict__ P,
         const int beam = u >> 2, q2 = u & 3;
         const int jj = beam >> 8, m = beam & 255;
         const int ss2 = (q2 + 2) & 3;  // q = s0 + 4 q2 holds s = s0 + 4 ss2
-        dst[beam * kUp + s0 + 4 * q2] = P[(ss2 * 4 + jj) * 512 + lut[m]];
+        const int idx = (ss2 * 4 + jj) * 512 + lut[m];
+        dst[beam * kUp + s0 + 4 * q2] = P2 ? P[idx] + P2[idx] : P[idx];
     }
 }
 

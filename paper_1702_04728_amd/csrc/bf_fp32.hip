@@ -155,17 +155,17 @@ void bf_fp32_kernel(LaunchArgs a)
     load_block(src, raw, t);
 
     float acc[2][16];
-    static_assert(sizeof(acc) == kAccPerThread * sizeof(float), "partial-sum layout");
+    constexpr int kAcc = sizeof(acc) / sizeof(float);
     if (io.first) {
 #pragma unroll
         for (int d = 0; d < 16; ++d) acc[0][d] = acc[1][d] = 0.f;
     } else {
-        load_partial(&acc[0][0], io.partial, t);
+        load_partial<kAcc>(&acc[0][0], io.partial, t);
     }
 
     for (int blk = 0; blk < a.n_blk; ++blk) {
         // A: time DFT of this thread's 8 inputs
-        time_dft_class(wk.s0, raw, T, t);
+        time_dft_class<false>(wk.s0, raw, T, t);
         __syncthreads();
         // prefetch the next block's samples while the transforms run
         if (blk + 1 < a.n_blk) load_block(src + (size_t)(blk + 1) * (kUp * kInputs), raw, t);
@@ -191,7 +191,7 @@ void bf_fp32_kernel(LaunchArgs a)
     }
 
     if (!io.last) {  // frame continues in the next chunk's launch
-        store_partial(&acc[0][0], io.partial, t);
+        store_partial<kAcc>(&acc[0][0], io.partial, t);
         return;
     }
     // per-bin powers -> LDS, then gather by the bin table into out[beam][q]
@@ -202,7 +202,7 @@ void bf_fp32_kernel(LaunchArgs a)
         P[g * 512 + 2 * b + 1 + 32 * d] = acc[1][d];
     }
     __syncthreads();
-    write_beams(P, a.lut + (size_t)io.row * kBeamNS, io.out, wk.s0, t);
+    write_beams(P, nullptr, a.lut + (size_t)io.row * kBeamNS, io.out, wk.s0, t);
 }
 
 }  // namespace

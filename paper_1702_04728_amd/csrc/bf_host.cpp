@@ -226,6 +226,12 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
     for (double v : p->cyl_x) if (!std::isfinite(v)) { delete p; return fail(nullptr, BF_E_INVAL, "cyl_x_m must be finite"); }
     for (double v : p->sin_phi) if (!std::isfinite(v)) { delete p; return fail(nullptr, BF_E_INVAL, "sin_phi_ew must be finite"); }
 
+    // Mirror symmetry of the E-W geometry (the default layout has it): then
+    // W[j][3-c] = W[3-j][c] = conj(W[j][c]) exactly and the kernels use half the
+    // E-W multiply-adds.
+    p->sym_ew = (p->cyl_x[3] == -p->cyl_x[0] && p->cyl_x[2] == -p->cyl_x[1] &&
+                 p->sin_phi[3] == -p->sin_phi[0] && p->sin_phi[2] == -p->sin_phi[1]) ? 1 : 0;
+
     p->lut.resize((size_t)n_chan * bf::kBeamNS);
     bf_config tmp = *cfg;
     tmp.sin_theta_ns = p->sin_theta.data();
@@ -311,6 +317,7 @@ int32_t beamform_frame(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float*
     a.n_time = p->cfg.n_time;
     a.st = nullptr;
     a.partial = nullptr;
+    a.sym_ew = p->sym_ew;
     e = p->cfg.precision == BF_FP16_MFMA ? bf::launch_mfma(a, (hipStream_t)stream)
                                          : bf::launch_fp32(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(p, e, "kernel launch");

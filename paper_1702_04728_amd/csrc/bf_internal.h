@@ -25,8 +25,8 @@ constexpr int kBeams = kBeamNS * kBeamEW;      // 1024
 constexpr int kUp = 16;                        // time-DFT length
 constexpr int kOutPerUnit = kBeams * kUp;      // floats per channel-frame
 
-constexpr int kAccPerThread = 32;              // per-bin power accumulators per thread
-constexpr int kPartialPerWg = 256 * kAccPerThread;  // floats of one workgroup's partial sums
+constexpr int kAccPerThreadMax = 64;          // per-bin power accumulators per thread (max over kernels)
+constexpr int kPartialPerWg = 256 * kAccPerThreadMax;  // floats of one workgroup's partial sums
 
 // Device state of one streaming launch (see beamform_stream).
 struct StreamState {
@@ -60,6 +60,7 @@ struct LaunchArgs {
     int32_t n_blk;         // 16-sample blocks per launch
     int32_t n_time;        // stream mode: samples per frame (ring entry stride)
     int32_t max_slots;     // stream mode: slots per ring entry
+    int32_t sym_ew;        // 1: x[3-c] = -x[c] and sin(phi[3-j]) = -sin(phi[j]) exactly
 };
 
 hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream);
@@ -84,5 +85,6 @@ struct bf_plan {
     float2* d_ew = nullptr;
     float2* d_tw = nullptr;
     void* d_mf = nullptr;
+    int32_t sym_ew = 0;              // geometry symmetric about the array centre
     std::string err;
 };

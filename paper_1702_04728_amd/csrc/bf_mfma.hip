@@ -58,19 +58,73 @@ __device__ __forceinline__ half8 pack_half8(const float2 (&v)[4])
     return h;
 }
 
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Low halves of the hi/lo split of (x0, x1), hpair = fp16(x0) | fp16(x1) << 16:
+// fp16(x - hi) computed by the mixed-precision FMA (x - hi is exact in FP32),
+// two instructions for two values.
+__device__ __forceinline__ uint32_t split_lo_pair(uint32_t hpair, float x0, float x1)
+{
+    uint32_t r;
+    asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixhi_f16 %0, %1, -1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+        : "=&v"(r)
+        : "v"(hpair), "v"(x0), "v"(x1));
+    return r;
+}
+
 // hi = fp16(v), lo = fp16(v - hi): together they carry ~22 significant bits.
 __device__ __forceinline__ void split_half8(const float2 (&v)[4], half8& hi, half8& lo)
 {
+    u32x4 h, l;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const _Float16 hx = (_Float16)v[i].x, hy = (_Float16)v[i].y;
-        hi[2 * i] = hx;
-        hi[2 * i + 1] = hy;
-        lo[2 * i] = (_Float16)(v[i].x - (float)hx);
-        lo[2 * i + 1] = (_Float16)(v[i].y - (float)hy);
+        half2v hp;
+        hp[0] = (_Float16)v[i].x;
+        hp[1] = (_Float16)v[i].y;
+        const uint32_t hb = __builtin_bit_cast(uint32_t, hp);
+        h[i] = hb;
+        l[i] = split_lo_pair(hb, v[i].x, v[i].y);
+    }
+    hi = __builtin_bit_cast(half8, h);
+    lo = __builtin_bit_cast(half8, l);
+}
+
+// E-W phasing of one (sub-channel, feed, pol) across the four cylinders:
+// b_j = sum_c W[j][c] y_c, written to v[j][ia] for j = 0..3.  With the mirror
+// symmetric geometry W[j][3-c] = W[3-j][c] = conj(W[j][c]), so with
+// S_c = y_c + y_(3-c), D_c = y_c - y_(3-c) (c = 0, 1):
+// b_j = P_j + i Q_j, b_(3-j) = P_j - i Q_j, P_j = sum Re W[j][c] S_c,
+// Q_j = sum Im W[j][c] D_c  (32 instead of 64 multiply-adds).
+template <bool kSym>
+__device__ __forceinline__ void ew_phase(const float2 (&y)[4], const float2 (&W)[4][4],
+                                         float2 (&v)[4][4], int ia)
+{
+    if constexpr (kSym) {
+        const float2 S0 = cadd(y[0], y[3]), S1 = cadd(y[1], y[2]);
+        const float2 D0 = csub(y[0], y[3]), D1 = csub(y[1], y[2]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const float2 P = make_float2(fmaf(W[j][0].x, S0.x, W[j][1].x * S1.x),
+                                         fmaf(W[j][0].x, S0.y, W[j][1].x * S1.y));
+            const float2 Q = make_float2(fmaf(W[j][0].y, D0.x, W[j][1].y * D1.x),
+                                         fmaf(W[j][0].y, D0.y, W[j][1].y * D1.y));
+            v[j][ia] = make_float2(P.x - Q.y, P.y + Q.x);
+            v[3 - j][ia] = make_float2(P.x + Q.y, P.y - Q.x);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc = cmac(acc, y[c], W[j][c]);
+            v[j][ia] = acc;
+        }
     }
 }
 
+template <bool kSym>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bf_mfma_kernel(LaunchArgs a)
 {
@@ -111,7 +165,7 @@ void bf_mfma_kernel(LaunchArgs a)
     load_block(src, raw, t);
 
     float acc[4][2][4];  // [E-W beam j][c = n + 16 nu][d = 4 q + i]
-    static_assert(sizeof(acc) == kAccPerThread * sizeof(float), "partial-sum layout");
+    constexpr int kAcc = sizeof(acc) / sizeof(float);
     if (io.first) {
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -120,34 +174,51 @@ void bf_mfma_kernel(LaunchArgs a)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) acc[j][nu][i] = 0.f;
     } else {
-        load_partial(&acc[0][0][0], io.partial, t);
+        load_partial<kAcc>(&acc[0][0][0], io.partial, t);
     }
 
     for (int blk = 0; blk < a.n_blk; ++blk) {
-        time_dft_class(wk.s0, raw, s_T, t);
+        time_dft_class<false>(wk.s0, raw, s_T, t);
         __syncthreads();
         if (blk + 1 < a.n_blk) load_block(src + (size_t)(blk + 1) * (kUp * kInputs), raw, t);
 
         // E-W phasing straight into stage-1 A fragments: feeds 16 a + n, a = 4q + ia
         half8 A[4][2];
+        if constexpr (kSym) {  // both pols per LDS read
+            float2 v[2][4][4];  // [p][j][ia]
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            float2 v[4][4];  // [j][ia]
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int ia = 0; ia < 4; ++ia) v[j][ia] = make_float2(0.f, 0.f);
-#pragma unroll
-            for (int ia = 0; ia < 4; ++ia)
+            for (int ia = 0; ia < 4; ++ia) {
+                float2 y0[4], y1[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const float4 x4 = s_T[s2 * 1024 + c * 256 + 16 * (4 * q + ia) + n];
-                    const float2 x = p ? make_float2(x4.z, x4.w) : make_float2(x4.x, x4.y);
+                    y0[c] = make_float2(x4.x, x4.y);
+                    y1[c] = make_float2(x4.z, x4.w);
+                }
+                ew_phase<kSym>(y0, W, v[0], ia);
+                ew_phase<kSym>(y1, W, v[1], ia);
+            }
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) v[j][ia] = cmac(v[j][ia], x, W[j][c]);
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) A[j][p] = pack_half8(v[p][j]);
+        } else {  // one pol at a time keeps the live set within 2 waves/SIMD
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                float2 v[4][4];  // [j][ia]
+#pragma unroll
+                for (int ia = 0; ia < 4; ++ia) {
+                    float2 y[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const float4 x4 = s_T[s2 * 1024 + c * 256 + 16 * (4 * q + ia) + n];
+                        y[c] = p ? make_float2(x4.z, x4.w) : make_float2(x4.x, x4.y);
+                    }
+                    ew_phase<kSym>(y, W, v, ia);
                 }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) A[j][p] = pack_half8(v[j]);
+                for (int j = 0; j < 4; ++j) A[j][p] = pack_half8(v[j]);
+            }
         }
         __syncthreads();
 
@@ -192,7 +263,7 @@ void bf_mfma_kernel(LaunchArgs a)
     }
 
     if (!io.last) {  // frame continues in the next chunk's launch
-        store_partial(&acc[0][0][0], io.partial, t);
+        store_partial<kAcc>(&acc[0][0][0], io.partial, t);
         return;
     }
     // per-bin powers -> LDS (bin k = c + 32 d), then gather into out[beam][q]
@@ -205,7 +276,7 @@ void bf_mfma_kernel(LaunchArgs a)
             for (int i = 0; i < 4; ++i)
                 P[(s2 * 4 + j) * 512 + n + 16 * nu + 32 * (4 * q + i)] = acc[j][nu][i];
     __syncthreads();
-    write_beams(P, a.lut + (size_t)io.row * kBeamNS, io.out, wk.s0, t);
+    write_beams(P, nullptr, a.lut + (size_t)io.row * kBeamNS, io.out, wk.s0, t);
 }
 
 }  // namespace
@@ -215,8 +286,9 @@ hipError_t launch_mfma(const LaunchArgs& a, hipStream_t stream)
     if (a.n_units <= 0) return hipSuccess;
     LaunchArgs args = a;
     void* params[] = {&args};
-    return hipLaunchKernel(reinterpret_cast<const void*>(&bf_mfma_kernel), dev::grid_for(a.n_units),
-                           dim3(dev::kThreads), params, 0, stream);
+    const void* k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true>)
+                             : reinterpret_cast<const void*>(&bf_mfma_kernel<false>);
+    return hipLaunchKernel(k, dev::grid_for(a.n_units), dim3(dev::kThreads), params, 0, stream);
 }
 
 }  // namespace bf

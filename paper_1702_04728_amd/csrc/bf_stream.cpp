@@ -301,6 +301,7 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     a.n_blk = chunk / bf::kUp;
     a.n_time = n_time;
     a.max_slots = S;
+    a.sym_ew = p->sym_ew;
     auto launch = [&](hipStream_t on) {
         return p->cfg.precision == BF_FP16_MFMA ? bf::launch_mfma(a, on) : bf::launch_fp32(a, on);
     };
