@@ -120,35 +120,67 @@ class Geometry:
 _lib = None
 
 
+def build_variant(src_text: str, out_path: str) -> str:
+    """Compile another oracle source (e.g. a deliberately broken copy used to check
+    that the pins detect mistakes) into out_path."""
+    src = out_path + ".c"
+    with open(src, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o",
+                           out_path, src, "-lm"])
+    return out_path
+
+
+class use_library:
+    """Context manager: route every oracle call through the library at `path`."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _lib = _bind(ctypes.CDLL(self.path))
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+
+
 def _load():
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(build())
-        vp = ctypes.c_void_p
-        i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-        gp = ctypes.POINTER(_Geom)
-        lib.orc_decode.argtypes = [vp, i64, vp]
-        lib.orc_decode.restype = None
-        lib.orc_lut.argtypes = [gp, f64, vp]
-        lib.orc_lut.restype = None
-        lib.orc_ns_beams.argtypes = [i32, i32, vp, i32, vp, vp]
-        lib.orc_ns_beams.restype = None
-        lib.orc_ew_weights.argtypes = [gp, f64, vp]
-        lib.orc_ew_weights.restype = None
-        lib.orc_ew_beams.argtypes = [i32, i32, vp, vp, vp]
-        lib.orc_ew_beams.restype = None
-        lib.orc_upchan.argtypes = [i32, vp, vp]
-        lib.orc_upchan.restype = None
-        lib.orc_beamform_unit.argtypes = [gp, f64, vp, vp, vp]
-        lib.orc_beamform_unit.restype = ctypes.c_int
-        lib.orc_beamform_units.argtypes = [gp, vp, i32, vp, vp, i32, vp, i32, vp, i32]
-        lib.orc_beamform_units.restype = ctypes.c_int
-        lib.orc_beamform.argtypes = [gp, vp, i32, vp, vp, i32, vp, i32]
-        lib.orc_beamform.restype = ctypes.c_int
-        lib.orc_max_threads.argtypes = []
-        lib.orc_max_threads.restype = ctypes.c_int
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(build()))
     return _lib
+
+
+def _bind(lib):
+    """Declare the C signatures on a loaded oracle library."""
+    vp = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    gp = ctypes.POINTER(_Geom)
+    lib.orc_decode.argtypes = [vp, i64, vp]
+    lib.orc_decode.restype = None
+    lib.orc_lut.argtypes = [gp, f64, vp]
+    lib.orc_lut.restype = None
+    lib.orc_ns_beams.argtypes = [i32, i32, vp, i32, vp, vp]
+    lib.orc_ns_beams.restype = None
+    lib.orc_ew_weights.argtypes = [gp, f64, vp]
+    lib.orc_ew_weights.restype = None
+    lib.orc_ew_beams.argtypes = [i32, i32, vp, vp, vp]
+    lib.orc_ew_beams.restype = None
+    lib.orc_upchan.argtypes = [i32, vp, vp]
+    lib.orc_upchan.restype = None
+    lib.orc_beamform_unit.argtypes = [gp, f64, vp, vp, vp]
+    lib.orc_beamform_unit.restype = ctypes.c_int
+    lib.orc_beamform_units.argtypes = [gp, vp, i32, vp, vp, i32, vp, i32, vp, i32]
+    lib.orc_beamform_units.restype = ctypes.c_int
+    lib.orc_beamform.argtypes = [gp, vp, i32, vp, vp, i32, vp, i32]
+    lib.orc_beamform.restype = ctypes.c_int
+    lib.orc_max_threads.argtypes = []
+    lib.orc_max_threads.restype = ctypes.c_int
+    return lib
 
 
 def _ptr(a: np.ndarray | None):

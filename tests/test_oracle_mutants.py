@@ -1,0 +1,84 @@
+"""The pins catch plausible mistakes in the oracle.
+
+Each case plants one mistake in a copy of oracle.c (on the CPU, in a temporary
+directory), builds it, routes the oracle binding through it and runs the pin
+suite: at least one pin must fail.  The real oracle is untouched.
+"""
+import inspect
+import os
+
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+
+SRC = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
+
+# (name, text in oracle.c, replacement)
+MUTANTS = [
+    ("eq1 without +0.5",
+     "* (g->feed_spacing_m / g->c0) * g->sin_theta_ns[m] + 0.5;",
+     "* (g->feed_spacing_m / g->c0) * g->sin_theta_ns[m];"),
+    ("eq1 truncation instead of floor",
+     "int64_t k = (int64_t)floor(t);", "int64_t k = (int64_t)t;"),
+    ("nibbles swapped",
+     "out[2 * i] = (double)((int)(in[i] >> 4) - 8);\n        out[2 * i + 1] = (double)((int)(in[i] & 15) - 8);",
+     "out[2 * i] = (double)((int)(in[i] & 15) - 8);\n        out[2 * i + 1] = (double)((int)(in[i] >> 4) - 8);"),
+    ("decode offset 7",
+     "out[2 * i] = (double)((int)(in[i] >> 4) - 8);", "out[2 * i] = (double)((int)(in[i] >> 4) - 7);"),
+    ("N-S conjugate phase",
+     "re += xr * wr - xi * wi;\n            im += xr * wi + xi * wr;\n            r += km;",
+     "re += xr * wr + xi * wi;\n            im += -xr * wi + xi * wr;\n            r += km;"),
+    ("N-S phase step off by one feed",
+     "            r += km;\n            if (r >= n_bins) r -= n_bins;",
+     "            r += km + (n == 0 ? km : 0);\n            while (r >= n_bins) r -= n_bins;"),
+    ("E-W weight sign",
+     "w[2 * (j * g->n_cyl + c) + 1] = -sin(a);", "w[2 * (j * g->n_cyl + c) + 1] = sin(a);"),
+    ("E-W weights transposed",
+     "double wr = w[2 * (j * n_cyl + c)], wi = w[2 * (j * n_cyl + c) + 1];",
+     "double wr = w[2 * (c * n_ew + j)], wi = w[2 * (c * n_ew + j) + 1];"),
+    ("no centre shift of sub-channels",
+     "int32_t q = (s + L / 2) % L;", "int32_t q = s;"),
+    ("time DFT sign",
+     "re += b[2 * t] * wr - b[2 * t + 1] * wi;\n            im += b[2 * t] * wi + b[2 * t + 1] * wr;",
+     "re += b[2 * t] * wr + b[2 * t + 1] * wi;\n            im += -b[2 * t] * wi + b[2 * t + 1] * wr;"),
+    ("power drops imaginary part",
+     "u[2 * s] * u[2 * s] + u[2 * s + 1] * u[2 * s + 1];", "u[2 * s] * u[2 * s];"),
+    ("last block not integrated",
+     "for (int32_t blk = 0; blk < T / L; ++blk) {", "for (int32_t blk = 0; blk < T / L - 1; ++blk) {"),
+    ("one polarisation only",
+     "            for (int32_t p = 0; p < NP; ++p)\n                for (int32_t blk",
+     "            for (int32_t p = 0; p < 1; ++p)\n                for (int32_t blk"),
+    ("input index feed-major",
+     "int64_t i = ((int64_t)c * NF + n) * NP + p;", "int64_t i = ((int64_t)c * NP + p) * NF + n;"),
+    ("beam index N-S major",
+     "out[((size_t)j * NM + m) * L + q] +=", "out[((size_t)m * NJ + j) * L + q] +="),
+]
+
+PIN_TESTS = [(name, fn) for name, fn in inspect.getmembers(pins, inspect.isfunction)
+             if name.startswith("test_")]
+
+
+def _run_pins(oracle_mod):
+    failed = []
+    for name, fn in PIN_TESTS:
+        kwargs = {"oracle_mod": oracle_mod} if "oracle_mod" in inspect.signature(fn).parameters else {}
+        try:
+            fn(**kwargs)
+        except Exception:
+            failed.append(name)
+    return failed
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(tmp_path, name, old, new):
+    assert SRC.count(old) == 1, "mutation anchor not unique: %s" % name
+    lib = oracle.build_variant(SRC.replace(old, new), str(tmp_path / "liboracle_mutant.so"))
+    with oracle.use_library(lib):
+        failed = _run_pins(oracle)
+    print("%s: caught by %s" % (name, failed))
+    assert failed, "no pin detects: %s" % name
+
+
+def test_unmodified_oracle_passes_all_pins():
+    assert _run_pins(oracle) == []
