@@ -35,16 +35,24 @@ BYTES_PER_UNIT = 384 * 2048 + 1024 * 16 * 4  # 851,968 algorithmic HBM bytes per
 # line 16,384 complex MACs (stage 1: 32 x 16 x 16, stage 2: 32 x 16 x 16), 8 lines
 # per sample, 8 real flops per complex MAC.
 FLOPS_PER_UNIT = {"fp32": 384 * (184_320 + 65_536 + 40_960 + 8_192),
-                  "fp16": 384 * 8 * 16_384 * 8}
+                  "fp16": 384 * 8 * 16_384 * 8,
+                  "fp32_mfma": 384 * 8 * 16_384 * 8}
 PEAK = {"fp32": (157.3, "TFLOP/s", "alu"),    # MI355X FP32 vector peak (published)
-        "fp16": (2500.0, "TFLOP/s", "mfma")}  # MI355X dense FP16 matrix peak
+        "fp16": (2500.0, "TFLOP/s", "mfma"),  # MI355X dense FP16 matrix peak
+        "fp32_mfma": (2500.0, "TFLOP/s", "mfma")}
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAME = {"fp32": "bf_fp32_kernel", "fp16": "bf_mfma_kernel"}
-DTYPE = {"fp32": "f32", "fp16": "f16 x f16 -> f32 (MFMA)"}
-PATH_NAME = {"fp32": "fp32_fft", "fp16": "fp16_mfma"}
+KERNEL_NAME = {"fp32": "bf_fp32_kernel", "fp16": "bf_mfma_kernel<true, false>",
+               "fp32_mfma": "bf_mfma_kernel<true, true>"}
+# directions without mirror symmetry (tracking beams) take the general E-W form
+KERNEL_NAME_GENERAL = {"fp32": "bf_fp32_kernel", "fp16": "bf_mfma_kernel<false, false>",
+                       "fp32_mfma": "bf_mfma_kernel<false, true>"}
+DTYPE = {"fp32": "f32", "fp16": "f16 x f16 -> f32 (MFMA)",
+         "fp32_mfma": "f16 hi+lo pairs -> f32 (MFMA, FP32-class)"}
+PATH_NAME = {"fp32": "fp32_fft", "fp16": "fp16_mfma", "fp32_mfma": "fp32_mfma"}
 _COMMON = ["paper_1702_04728_amd/csrc/bf_device.h", "paper_1702_04728_amd/csrc/bf_internal.h"]
 KERNEL_SOURCES = {"fp32": ["paper_1702_04728_amd/csrc/bf_fp32.hip"] + _COMMON,
-                  "fp16": ["paper_1702_04728_amd/csrc/bf_mfma.hip"] + _COMMON}
+                  "fp16": ["paper_1702_04728_amd/csrc/bf_mfma.hip"] + _COMMON,
+                  "fp32_mfma": ["paper_1702_04728_amd/csrc/bf_mfma.hip"] + _COMMON}
 
 
 def log(*a):
@@ -106,14 +114,15 @@ def copy_probe(torch, mib: int, reps: int):
     log("copy probe: %d x %d MiB" % (reps, mib))
 
 
-def time_path(torch, bf, prec, raw, freqs, units, args):
-    """Warm up, then time args.steps launches of one path on the current stream."""
+def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None):
+    """Warm up, then time args.steps launches of one path on the current stream.
+    sin_phi: per-frame E-W directions (tracking beams), or None for static beams."""
     beam = bf.Beamformer(freqs, precision=prec)
     n_frames = raw.shape[0]
     out = torch.empty(beam.out_shape(n_frames), dtype=torch.float32, device=raw.device)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
-        beam.frame(raw, out)
+        beam.frame(raw, out, sin_phi_ew=sin_phi)
     torch.cuda.synchronize()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -123,7 +132,7 @@ def time_path(torch, bf, prec, raw, freqs, units, args):
     ev0.record(stream)
     for i in range(args.steps):
         starts[i].record(stream)
-        beam.frame(raw, out)
+        beam.frame(raw, out, sin_phi_ew=sin_phi)
         ends[i].record(stream)
     ev1.record(stream)
     torch.cuda.synchronize()
@@ -131,7 +140,8 @@ def time_path(torch, bf, prec, raw, freqs, units, args):
     per = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     ms_step = total_ms / args.steps
     beam.close()
-    log("%s: timed %d steps: %.4f ms/step (events)" % (prec, args.steps, ms_step))
+    log("%s%s: timed %d steps: %.4f ms/step (events)"
+        % (prec, "" if sin_phi is None else " tracking", args.steps, ms_step))
     kern_s = float(np.mean(per)) * 1e-3
     flops = FLOPS_PER_UNIT[prec] * units
     peak, punit, bound = PEAK[prec]
@@ -142,8 +152,9 @@ def time_path(torch, bf, prec, raw, freqs, units, args):
         "dtype": DTYPE[prec],
         "roofline": {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
                      "unit": punit, "frac": round(achieved / peak, 4),
-                     "traffic": traffic_from_profiles(prec, units),
-                     "kernel": KERNEL_NAME[prec], "flops_per_launch": flops},
+                     "traffic": traffic_from_profiles(prec, units) if sin_phi is None else None,
+                     "kernel": (KERNEL_NAME if sin_phi is None else KERNEL_NAME_GENERAL)[prec],
+                     "flops_per_launch": flops},
         "hbm": {"achieved_GBs": round(BYTES_PER_UNIT * units / kern_s / 1e9, 1),
                 "peak_GBs": HBM_PEAK_GBS,
                 "frac": round(BYTES_PER_UNIT * units / kern_s / 1e9 / HBM_PEAK_GBS, 4),
@@ -233,10 +244,14 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=128)
-    ap.add_argument("--precision", default="both", choices=["fp32", "fp16", "both"],
-                    help="path(s) to time; with both, value is the FP32 path's")
+    ap.add_argument("--precision", default="all", choices=["fp32", "fp16", "fp32_mfma", "all"],
+                    help="path(s) to time; with all, value is the FP32 FFT path's")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tracking", action="store_true",
+                    help="skip the tracking E-W beam measurement")
+    ap.add_argument("--no-fullband", action="store_true",
+                    help="skip the 1024-channel measurement")
     ap.add_argument("--serve-frames", type=int, default=10000,
                     help="frames of the paced serving loop per path (0 skips it)")
     ap.add_argument("--sweep", action="store_true",
@@ -270,10 +285,30 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     raw = torch.from_numpy(raw_np).to(dev)
-    paths = ["fp32", "fp16"] if args.precision == "both" else [args.precision]
+    paths = ["fp32", "fp16", "fp32_mfma"] if args.precision == "all" else [args.precision]
     results = {}
     for prec in paths:
         results[prec] = time_path(torch, bf, prec, raw, freqs, units, args)
+    if not args.no_tracking:
+        # tracking E-W beams: beam 2 follows a source at 0.3 deg drifting at the
+        # sidereal rate (15 deg/h); weights recomputed on the host per call
+        phi = 0.3 + (15.0 / 3600.0) * FRAME_S * np.arange(raw.shape[0])
+        track = synth.tracking_pointings(phi)
+        for prec in paths:
+            results[prec]["tracking"] = time_path(torch, bf, prec, raw, freqs, units, args,
+                                                  sin_phi=track)
+    if not args.no_fullband:
+        # all 1024 channels of the band (400-800 MHz), two frames per launch: the
+        # workload's bytes tiled over the band, each channel with its own tables
+        f_all = synth.chan_freq_hz(np.arange(1024))
+        n_rep = (2 * 1024) // units + 1
+        raw_all = raw.reshape(units, -1).repeat(n_rep, 1).reshape(-1)[:2 * 1024 * raw[0, 0].numel()]
+        raw_all = raw_all.reshape(2, 1024, raw.shape[2], raw.shape[3]).contiguous()
+        for prec in paths:
+            r = time_path(torch, bf, prec, raw_all, f_all, 2048, args)
+            r["frames_per_s_all_1024_channels"] = round(2 / (r["ms_per_step"] * 1e-3), 1)
+            results[prec]["fullband"] = r
+        del raw_all
     if args.copy_probe_mib:
         copy_probe(torch, args.copy_probe_mib, 3)
 

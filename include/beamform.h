@@ -59,10 +59,16 @@ extern "C" {
 
 typedef struct bf_plan bf_plan; /* opaque, library-owned */
 
-/* Arithmetic of the N-S transform.  BF_FP32_FFT: FP32 radix FFT (the baseline,
- * <= 1e-5 relative power error against an FP64 evaluation).  BF_FP16_MFMA:
- * four-step 512 = 32 x 16 DFT on FP16 matrix cores with FP32 accumulation. */
-typedef enum { BF_FP32_FFT = 0, BF_FP16_MFMA = 1 } bf_precision;
+/* Arithmetic of the N-S transform.
+ *   BF_FP32_FFT:  FP32 radix FFT (the baseline, <= 1e-5 relative power error
+ *                 against an FP64 evaluation).
+ *   BF_FP16_MFMA: four-step 512 = 32 x 16 DFT on FP16 matrix cores with FP32
+ *                 accumulation (<= 2e-3; DFT matrices and the inter-stage data
+ *                 carried as FP16 hi + lo pairs, the E-W output rounded once).
+ *   BF_FP32_MFMA: the same matrix-core transform with every operand carried as
+ *                 FP16 hi + lo (about 22 significant bits): FP32-class error,
+ *                 <= 1e-5 like BF_FP32_FFT. */
+typedef enum { BF_FP32_FFT = 0, BF_FP16_MFMA = 1, BF_FP32_MFMA = 2 } bf_precision;
 
 typedef struct {
     int32_t n_cyl;      /* cylinders: must be 4 */
@@ -114,6 +120,24 @@ int32_t beamform_init(const bf_config *cfg, const double *chan_freq_hz, int32_t 
  * n_frames = 0 is a valid no-op.  Asynchronous on `stream`. */
 int32_t beamform_frame(bf_plan *plan, const uint8_t *d_in, int32_t n_frames, float *d_out,
                        void *stream);
+
+/* Tracking E-W beams (Sec. 3.1: the E-W beams may be static or tracking).  As
+ * beamform_frame, with the E-W directions given per frame instead of the
+ * plan's static ones:
+ *   sin_phi_ew: host FP64 [n_frames][n_beam_ew], sin(phi_j) of each frame.
+ * W[frame][chan][j][c] = exp(-2 pi i f_chan x_c sin(phi_{frame,j}) / c) is
+ * evaluated on the host in FP64, rounded once to FP32 and uploaded on `stream`
+ * into one of two plan-owned device tables used in turn (128 B per
+ * channel-frame each, grown when a call needs more: the first calls of a given
+ * size allocate); each channel-frame reads its own row.  N-S beams, bins and
+ * output layout are those of beamform_frame.  sin_phi_ew is read before the
+ * call returns.  A call blocks until the kernel of the call before last has
+ * finished (it reuses that call's table), so the host computes one table
+ * while the previous kernel runs; calls on one plan must be issued from one
+ * host thread.  Errors: BF_E_INVAL
+ * (NULL or non-finite sin_phi_ew, bad buffers), BF_E_NOMEM, BF_E_DEVICE. */
+int32_t beamform_frame_tracking(bf_plan *plan, const uint8_t *d_in, int32_t n_frames,
+                                const double *sin_phi_ew, float *d_out, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Streaming (serving) loop.  Frames of 0.983 ms arrive for a varying set of

@@ -7,7 +7,7 @@ integration to 0.983 ms -- runs in hand-written HIP kernels for gfx950 inside
 thin Python binding over it.
 """
 from .beamform import (  # noqa: F401
-    BF_OK, EXPORTED, FP16_MFMA, FP32_FFT, LIB_PATH, N_BEAMS, N_INPUTS, N_UPCHAN,
+    BF_OK, EXPORTED, FP16_MFMA, FP32_FFT, FP32_MFMA, LIB_PATH, N_BEAMS, N_INPUTS, N_UPCHAN,
     STREAM_JOIN, STREAM_LEAVE, STREAM_MAX_SLOTS, Beamformer, BeamformError, compute_lut,
     load_library, stream_schedule,
 )

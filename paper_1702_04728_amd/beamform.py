@@ -17,7 +17,9 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbeamform
 BF_OK = 0
 FP32_FFT = 0
 FP16_MFMA = 1
-_PRECISION = {"fp32": FP32_FFT, "fp16": FP16_MFMA, FP32_FFT: FP32_FFT, FP16_MFMA: FP16_MFMA}
+FP32_MFMA = 2
+_PRECISION = {"fp32": FP32_FFT, "fp16": FP16_MFMA, "fp32_mfma": FP32_MFMA,
+              FP32_FFT: FP32_FFT, FP16_MFMA: FP16_MFMA, FP32_MFMA: FP32_MFMA}
 
 N_INPUTS = 2048
 N_BEAMS = 1024
@@ -27,7 +29,7 @@ N_BEAM_NS = 256
 # Every symbol include/beamform.h declares.
 EXPORTED = (
     "beamform_default_config", "beamform_compute_lut", "beamform_init", "beamform_frame",
-    "beamform_stream", "beamform_stream_schedule", "beamform_get_lut", "beamform_plan_info",
+    "beamform_frame_tracking", "beamform_stream", "beamform_stream_schedule", "beamform_get_lut", "beamform_plan_info",
     "beamform_destroy", "beamform_strerror", "beamform_last_error",
 )
 
@@ -145,6 +147,7 @@ def load_library():
         "beamform_compute_lut": ([cp, vp, i32, vp], i32),
         "beamform_init": ([cp, vp, i32, vp, ctypes.POINTER(vp)], i32),
         "beamform_frame": ([vp, vp, i32, vp, vp], i32),
+        "beamform_frame_tracking": ([vp, vp, i32, vp, vp, vp], i32),
         "beamform_stream": ([vp, ctypes.POINTER(BfStreamDesc), ctypes.POINTER(BfStreamStats), vp],
                             i32),
         "beamform_stream_schedule": ([ctypes.POINTER(BfStreamDesc), ctypes.c_int64,
@@ -264,7 +267,10 @@ class Beamformer:
     def out_shape(self, n_frames: int):
         return (n_frames, self.n_chan, N_BEAMS, N_UPCHAN)
 
-    def frame(self, raw, out=None, stream=None):
+    def frame(self, raw, out=None, stream=None, sin_phi_ew=None):
+        """Beamform raw [n_frames][n_chan][n_time][2048] (CUDA uint8) into out
+        [n_frames][n_chan][1024][16] (CUDA float32).  sin_phi_ew: None for the plan's
+        static E-W beams, or [n_frames][4] E-W directions per frame (tracking beams)."""
         import torch
         if self._plan is None:
             raise BeamformError(-4, "plan destroyed")
@@ -282,8 +288,17 @@ class Beamformer:
                 and out.is_contiguous() and tuple(out.shape) == self.out_shape(n_frames)):
             raise ValueError("out must be a contiguous CUDA float32 tensor of shape %s"
                              % (self.out_shape(n_frames),))
-        st = self.lib.beamform_frame(self._plan, ctypes.c_void_p(raw.data_ptr()), n_frames,
-                                     ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+        if sin_phi_ew is None:
+            st = self.lib.beamform_frame(self._plan, ctypes.c_void_p(raw.data_ptr()), n_frames,
+                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+        else:
+            phi = np.ascontiguousarray(sin_phi_ew, dtype=np.float64)
+            if phi.shape != (n_frames, 4):
+                raise ValueError("sin_phi_ew must be [n_frames][4], got %s" % (phi.shape,))
+            st = self.lib.beamform_frame_tracking(
+                self._plan, ctypes.c_void_p(raw.data_ptr()), n_frames,
+                ctypes.c_void_p(phi.ctypes.data), ctypes.c_void_p(out.data_ptr()),
+                _stream_handle(stream))
         _check(st, self._plan)
         return out
 

@@ -116,7 +116,8 @@ struct UnitIO {
     const uint8_t* in;
     float* out;
     float* partial;  // this workgroup's partial sums (stream mode), else nullptr
-    int row;         // row of the bin table and E-W weights
+    int row;         // row of the bin table (and of the static E-W weights)
+    int ew_row;      // row of the E-W weights
     bool first, last;
 };
 // False when the workgroup has no unit (uniform across the workgroup).
@@ -128,6 +129,7 @@ __device__ __forceinline__ bool resolve_unit(const LaunchArgs& a, const Work& wk
         io.out = a.out + (size_t)wk.unit * kOutPerUnit;
         io.partial = nullptr;
         io.row = wk.unit % a.n_chan;
+        io.ew_row = a.ew_by_unit ? wk.unit : io.row;
         io.first = io.last = true;
         return true;
     }
@@ -139,6 +141,7 @@ __device__ __forceinline__ bool resolve_unit(const LaunchArgs& a, const Work& wk
     io.out = a.out + entry * kOutPerUnit;
     io.partial = a.partial + ((size_t)slot * 4 + wk.s0) * kPartialPerWg;
     io.row = slot;
+    io.ew_row = slot;
     io.first = chunk == 0;
     io.last = chunk == a.st->n_chunks - 1;
     return true;
@@ -167,10 +170,8 @@ __device__ __forceinline__ void store_partial(const float* acc, float* __restric
 //   T[s2] = sum_t1 (y[t1] w16^(t1 S0)) (-i)^(t1 s2)
 // y is formed on the raw nibbles four inputs at a time (bytewise integer
 // sums in a 32-bit word, biased so no byte borrows), converted to float once.
-// Output (kPolPlanes = false): T[s2 * 1024 + slot] float4 = both pols of
-// slot = cyl * 256 + feed; (kPolPlanes = true): float2 planes
-// T[(s2 * 2 + pol) * 1024 + slot].
-template <int S0, bool kPolPlanes>
+// Output: T[s2 * 1024 + slot], slot = cyl * 256 + feed, float4 = both pols.
+template <int S0>
 __device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restrict__ T, int t)
 {
     // nibble planes: re[tau][w], im[tau][w] hold the 4 offset-binary nibbles
@@ -224,28 +225,19 @@ __device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restr
 #pragma unroll
             for (int s2 = 0; s2 < 4; ++s2) o[p][s2] = y[s2];
         }
-        if constexpr (kPolPlanes) {
-            float2* T2 = reinterpret_cast<float2*>(T);
 #pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2)
-#pragma unroll
-                for (int p = 0; p < 2; ++p) T2[(s2 * 2 + p) * 1024 + 4 * t + h] = o[p][s2];
-        } else {
-#pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2)
-                T[s2 * 1024 + 4 * t + h] = make_float4(o[0][s2].x, o[0][s2].y, o[1][s2].x, o[1][s2].y);
-        }
+        for (int s2 = 0; s2 < 4; ++s2)
+            T[s2 * 1024 + 4 * t + h] = make_float4(o[0][s2].x, o[0][s2].y, o[1][s2].x, o[1][s2].y);
     }
 }
 
-template <bool kPolPlanes>
 __device__ __forceinline__ void time_dft_class(int s0, const uint2 (&raw)[16], float4* T, int t)
 {
     switch (s0) {
-    case 0: time_dft<0, kPolPlanes>(raw, T, t); break;
-    case 1: time_dft<1, kPolPlanes>(raw, T, t); break;
-    case 2: time_dft<2, kPolPlanes>(raw, T, t); break;
-    default: time_dft<3, kPolPlanes>(raw, T, t); break;
+    case 0: time_dft<0>(raw, T, t); break;
+    case 1: time_dft<1>(raw, T, t); break;
+    case 2: time_dft<2>(raw, T, t); break;
+    default: time_dft<3>(raw, T, t); break;
     }
 }
 
@@ -258,12 +250,10 @@ __device__ __forceinline__ void load_block(const uint8_t* __restrict__ blk, uint
         raw[tau] = *reinterpret_cast<const uint2*>(blk + tau * kInputs + 8 * t);
 }
 
-// End of frame: P[(s2 * 4 + j) * 512 + k] (plus P2[...] when the two
-// polarisations were integrated separately) holds the integrated power of FFT
+// End of frame: P[(s2 * 4 + j) * 512 + k] holds the integrated power of FFT
 // bin k for sub-channel s0 + 4 s2 and E-W beam j.  Beam (j, m) takes bin
 // lut[m] (Eq. (1)); sub-channel q holds time-DFT bin (q + 8) mod 16.
 __device__ __forceinline__ void write_beams(const float* __restrict__ P,
-                                            const float* __restrict__ P2,
                                             const int32_t* __restrict__ lut,
                                             float* __restrict__ dst, int s0, int t)
 {
@@ -273,8 +263,7 @@ __device__ __forceinline__ void write_beams(const float* __restrict__ P,
         const int beam = u >> 2, q2 = u & 3;
         const int jj = beam >> 8, m = beam & 255;
         const int ss2 = (q2 + 2) & 3;  // q = s0 + 4 q2 holds s = s0 + 4 ss2
-        const int idx = (ss2 * 4 + jj) * 512 + lut[m];
-        dst[beam * kUp + s0 + 4 * q2] = P2 ? P[idx] + P2[idx] : P[idx];
+        dst[beam * kUp + s0 + 4 * q2] = P[(ss2 * 4 + jj) * 512 + lut[m]];
     }
 }
 

@@ -144,7 +144,7 @@ void bf_fp32_kernel(LaunchArgs a)
     for (int i = t; i < 32 * 16; i += kThreads) s_tw[i] = a.tw[i];
     float2 W[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) W[c] = a.ew[((size_t)io.row * kBeamEW + j) * kCyl + c];
+    for (int c = 0; c < 4; ++c) W[c] = a.ew[((size_t)io.ew_row * kBeamEW + j) * kCyl + c];
 
     const uint8_t* src = io.in;
     float4* T = reinterpret_cast<float4*>(s_union);
@@ -165,7 +165,7 @@ void bf_fp32_kernel(LaunchArgs a)
 
     for (int blk = 0; blk < a.n_blk; ++blk) {
         // A: time DFT of this thread's 8 inputs
-        time_dft_class<false>(wk.s0, raw, T, t);
+        time_dft_class(wk.s0, raw, T, t);
         __syncthreads();
         // prefetch the next block's samples while the transforms run
         if (blk + 1 < a.n_blk) load_block(src + (size_t)(blk + 1) * (kUp * kInputs), raw, t);
@@ -202,7 +202,7 @@ void bf_fp32_kernel(LaunchArgs a)
         P[g * 512 + 2 * b + 1 + 32 * d] = acc[1][d];
     }
     __syncthreads();
-    write_beams(P, nullptr, a.lut + (size_t)io.row * kBeamNS, io.out, wk.s0, t);
+    write_beams(P, a.lut + (size_t)io.row * kBeamNS, io.out, wk.s0, t);
 }
 
 }  // namespace

@@ -18,7 +18,7 @@
 #include <new>
 #include <string>
 
-#include "bf_internal.h"
+#include "bf_plan.h"
 
 namespace {
 
@@ -56,7 +56,8 @@ int32_t check_config(const bf_config* c, std::string* msg)
         return BF_E_INVAL;
     }
     if (c->reserved != 0) { *msg = "reserved must be 0"; return BF_E_INVAL; }
-    if (c->precision != BF_FP32_FFT && c->precision != BF_FP16_MFMA) {
+    if (c->precision != BF_FP32_FFT && c->precision != BF_FP16_MFMA &&
+        c->precision != BF_FP32_MFMA) {
         *msg = "unknown precision";
         return BF_E_INVAL;
     }
@@ -106,6 +107,67 @@ int32_t fill_lut(const bf_config* c, const double* freqs, int32_t n_chan, int32_
             out[(size_t)ch * c->n_beam_ns + m] = k;
         }
     }
+    return BF_OK;
+}
+
+// E-W phases of one channel, W[j][c] = exp(-2 pi i f x_c sin(phi_j) / c0)
+// (Sec. 3 first kernel, Sec. 3.1), in FP64 and rounded once to FP32.
+void fill_ew(double f_hz, const double* cyl_x, const double* sin_phi, double c0, float2* w)
+{
+    for (int j = 0; j < bf::kBeamEW; ++j)
+        for (int c = 0; c < bf::kCyl; ++c) {
+            const double a = kTwoPi * f_hz * cyl_x[c] * sin_phi[j] / c0;
+            w[j * bf::kCyl + c] = make_float2((float)std::cos(a), (float)-std::sin(a));
+        }
+}
+
+// Mirror symmetry of the E-W geometry (the default layout has it): then
+// W[j][3-c] = W[3-j][c] = conj(W[j][c]) exactly and the kernels use half the
+// E-W multiply-adds.
+bool mirror_symmetric(const double* cyl_x, const double* sin_phi)
+{
+    return cyl_x[3] == -cyl_x[0] && cyl_x[2] == -cyl_x[1] &&
+           sin_phi[3] == -sin_phi[0] && sin_phi[2] == -sin_phi[1];
+}
+
+// Checks shared by the batch entry points, then one launch over all units.
+int32_t launch_batch(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float* d_out,
+                     hipStream_t stream, const float2* ew, int32_t ew_by_unit, int32_t sym)
+{
+    bf::LaunchArgs a{};
+    a.in = d_in;
+    a.out = d_out;
+    a.lut = p->d_lut;
+    a.ew = ew;
+    a.tw = p->d_tw;
+    a.mf = p->d_mf;
+    a.n_chan = p->n_chan;
+    a.n_units = n_frames * p->n_chan;
+    a.n_blk = p->cfg.n_time / bf::kUp;
+    a.n_time = p->cfg.n_time;
+    a.st = nullptr;
+    a.partial = nullptr;
+    a.sym_ew = sym;
+    a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
+    a.ew_by_unit = ew_by_unit;
+    hipError_t e = p->cfg.precision == BF_FP32_FFT ? bf::launch_fp32(a, stream)
+                                                   : bf::launch_mfma(a, stream);
+    if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
+    return BF_OK;
+}
+
+int32_t check_batch(bf_plan* p, const uint8_t* d_in, int32_t n_frames, const float* d_out)
+{
+    if (n_frames < 0) return fail(p, BF_E_INVAL, "n_frames < 0");
+    if (n_frames == 0) return BF_OK;
+    if (!d_in || !d_out) return fail(p, BF_E_INVAL, "NULL device buffer");
+    if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 15))
+        return fail(p, BF_E_INVAL, "device buffers must be 16-byte aligned");
+    if ((long long)n_frames * p->n_chan > (1LL << 26)) return fail(p, BF_E_INVAL, "batch too large");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(p, e, "hipGetDevice");
+    if (dev != p->device) return fail(p, BF_E_STATE, "current device differs from the plan's device");
     return BF_OK;
 }
 
@@ -226,11 +288,7 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
     for (double v : p->cyl_x) if (!std::isfinite(v)) { delete p; return fail(nullptr, BF_E_INVAL, "cyl_x_m must be finite"); }
     for (double v : p->sin_phi) if (!std::isfinite(v)) { delete p; return fail(nullptr, BF_E_INVAL, "sin_phi_ew must be finite"); }
 
-    // Mirror symmetry of the E-W geometry (the default layout has it): then
-    // W[j][3-c] = W[3-j][c] = conj(W[j][c]) exactly and the kernels use half the
-    // E-W multiply-adds.
-    p->sym_ew = (p->cyl_x[3] == -p->cyl_x[0] && p->cyl_x[2] == -p->cyl_x[1] &&
-                 p->sin_phi[3] == -p->sin_phi[0] && p->sin_phi[2] == -p->sin_phi[1]) ? 1 : 0;
+    p->sym_ew = mirror_symmetric(p->cyl_x.data(), p->sin_phi.data()) ? 1 : 0;
 
     p->lut.resize((size_t)n_chan * bf::kBeamNS);
     bf_config tmp = *cfg;
@@ -245,12 +303,8 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
     // E-W weights and N-S twiddles in FP64, rounded once.
     std::vector<float2> ew((size_t)n_chan * bf::kBeamEW * bf::kCyl);
     for (int32_t ch = 0; ch < n_chan; ++ch)
-        for (int j = 0; j < bf::kBeamEW; ++j)
-            for (int c = 0; c < bf::kCyl; ++c) {
-                const double a = kTwoPi * p->freqs[ch] * p->cyl_x[c] * p->sin_phi[j] / cfg->c0;
-                ew[((size_t)ch * bf::kBeamEW + j) * bf::kCyl + c] =
-                    make_float2((float)std::cos(a), (float)-std::sin(a));
-            }
+        fill_ew(p->freqs[ch], p->cyl_x.data(), p->sin_phi.data(), cfg->c0,
+                &ew[(size_t)ch * bf::kBeamEW * bf::kCyl]);
     std::vector<float2> tw(32 * 16);
     for (int c = 0; c < 32; ++c)
         for (int b = 0; b < 16; ++b) {
@@ -292,36 +346,61 @@ int32_t beamform_frame(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float*
 {
     if (!p) return BF_E_INVAL;
     p->err.clear();
-    if (n_frames < 0) return fail(p, BF_E_INVAL, "n_frames < 0");
-    if (n_frames == 0) return BF_OK;
-    if (!d_in || !d_out) return fail(p, BF_E_INVAL, "NULL device buffer");
-    if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 15))
-        return fail(p, BF_E_INVAL, "device buffers must be 16-byte aligned");
-    const long long units = (long long)n_frames * p->n_chan;
-    if (units > (1LL << 26)) return fail(p, BF_E_INVAL, "batch too large");
-    int dev = -1;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(p, e, "hipGetDevice");
-    if (dev != p->device) return fail(p, BF_E_STATE, "current device differs from the plan's device");
+    int32_t st = check_batch(p, d_in, n_frames, d_out);
+    if (st != BF_OK || n_frames == 0) return st;
+    return launch_batch(p, d_in, n_frames, d_out, (hipStream_t)stream, p->d_ew, 0, p->sym_ew);
+}
 
-    bf::LaunchArgs a{};
-    a.in = d_in;
-    a.out = d_out;
-    a.lut = p->d_lut;
-    a.ew = p->d_ew;
-    a.tw = p->d_tw;
-    a.mf = p->d_mf;
-    a.n_chan = p->n_chan;
-    a.n_units = (int32_t)units;
-    a.n_blk = p->cfg.n_time / bf::kUp;
-    a.n_time = p->cfg.n_time;
-    a.st = nullptr;
-    a.partial = nullptr;
-    a.sym_ew = p->sym_ew;
-    e = p->cfg.precision == BF_FP16_MFMA ? bf::launch_mfma(a, (hipStream_t)stream)
-                                         : bf::launch_fp32(a, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
-    return BF_OK;
+int32_t beamform_frame_tracking(bf_plan* p, const uint8_t* d_in, int32_t n_frames,
+                                const double* sin_phi_ew, float* d_out, void* stream)
+{
+    if (!p) return BF_E_INVAL;
+    p->err.clear();
+    int32_t st = check_batch(p, d_in, n_frames, d_out);
+    if (st != BF_OK || n_frames == 0) return st;
+    if (!sin_phi_ew) return fail(p, BF_E_INVAL, "sin_phi_ew is NULL");
+    bool sym = true;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        const double* s = sin_phi_ew + (size_t)f * bf::kBeamEW;
+        for (int j = 0; j < bf::kBeamEW; ++j)
+            if (!std::isfinite(s[j])) return fail(p, BF_E_INVAL, "sin_phi_ew must be finite");
+        sym = sym && mirror_symmetric(p->cyl_x.data(), s);
+    }
+    const size_t rows = (size_t)n_frames * p->n_chan, row_b = bf::kBeamEW * bf::kCyl * sizeof(float2);
+    bf_plan::EwTrack& t = p->ew_track[p->ew_track_next];
+    hipError_t e = hipSuccess;
+    if (!t.done && (e = hipEventCreateWithFlags(&t.done, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(p, e, "hipEventCreate");
+    // The kernel of the call before last may still read this buffer pair and its
+    // upload may still read the staging half: wait for it before reuse.
+    if ((e = hipEventSynchronize(t.done)) != hipSuccess)
+        return hip_fail(p, e, "previous tracking call");
+    if (rows > t.cap) {
+        if (t.d) (void)hipFree(t.d);
+        if (t.h) (void)hipHostFree(t.h);
+        t.d = nullptr;
+        t.h = nullptr;
+        t.cap = 0;
+        if ((e = hipMalloc(&t.d, rows * row_b)) != hipSuccess ||
+            (e = hipHostMalloc((void**)&t.h, rows * row_b, hipHostMallocDefault)) != hipSuccess) {
+            if (t.d) (void)hipFree(t.d);
+            t.d = nullptr;
+            return fail(p, BF_E_NOMEM, std::string("tracking table: ") + hipGetErrorString(e));
+        }
+        t.cap = rows;
+    }
+    for (int32_t f = 0; f < n_frames; ++f)
+        for (int32_t ch = 0; ch < p->n_chan; ++ch)
+            fill_ew(p->freqs[ch], p->cyl_x.data(), sin_phi_ew + (size_t)f * bf::kBeamEW, p->cfg.c0,
+                    t.h + ((size_t)f * p->n_chan + ch) * bf::kBeamEW * bf::kCyl);
+    hipStream_t s = (hipStream_t)stream;
+    if ((e = hipMemcpyAsync(t.d, t.h, rows * row_b, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(p, e, "tracking table upload");
+    st = launch_batch(p, d_in, n_frames, d_out, s, t.d, 1, sym ? 1 : 0);
+    if ((e = hipEventRecord(t.done, s)) != hipSuccess && st == BF_OK)
+        st = hip_fail(p, e, "hipEventRecord");
+    p->ew_track_next ^= 1;
+    return st;
 }
 
 int32_t beamform_get_lut(const bf_plan* p, int32_t* host_out)
@@ -351,6 +430,11 @@ int32_t beamform_destroy(bf_plan* p)
     if (p->d_ew) (void)hipFree(p->d_ew);
     if (p->d_tw) (void)hipFree(p->d_tw);
     if (p->d_mf) (void)hipFree(p->d_mf);
+    for (bf_plan::EwTrack& t : p->ew_track) {
+        if (t.d) (void)hipFree(t.d);
+        if (t.h) (void)hipHostFree(t.h);
+        if (t.done) (void)hipEventDestroy(t.done);
+    }
     if (prev >= 0 && prev != p->device) (void)hipSetDevice(prev);
     delete p;
     return st;

@@ -4,8 +4,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <string>
-#include <vector>
 
 #include "beamform.h"
 
@@ -46,6 +44,8 @@ constexpr size_t kStreamStateHeader = 4 * sizeof(int32_t);
 //     [chunk_index * n_blk * 16, +n_blk * 16) of in[e][n_time][2048], tables
 //     row slot, keeps per-bin partial sums in partial[slot][4][kPartialPerWg]
 //     between chunks and writes out[e] at the frame's last chunk.
+// With ew_by_unit (batch mode only) the E-W weights are per channel-frame:
+// row u of ew instead of row u % n_chan (tracking beams).
 struct LaunchArgs {
     const uint8_t* in;
     float* out;
@@ -61,6 +61,8 @@ struct LaunchArgs {
     int32_t n_time;        // stream mode: samples per frame (ring entry stride)
     int32_t max_slots;     // stream mode: slots per ring entry
     int32_t sym_ew;        // 1: x[3-c] = -x[c] and sin(phi[3-j]) = -sin(phi[j]) exactly
+    int32_t split_v;       // matrix-core path: 1 = E-W output also as hi + lo (FP32-class)
+    int32_t ew_by_unit;    // 1: ew has one row per unit (batch mode)
 };
 
 hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream);
@@ -74,17 +76,3 @@ constexpr size_t kMfmaTableBytes = (8 * 64 + 4 * 64) * 16 + 64 * 8 * 8;
 void build_mfma_tables(void* host_buf);
 
 }  // namespace bf
-
-struct bf_plan {
-    bf_config cfg{};                 // host-array pointers cleared; copies below
-    std::vector<double> cyl_x, sin_theta, sin_phi, freqs;
-    std::vector<int32_t> lut;        // [n_chan][256]
-    int32_t n_chan = 0;
-    int device = 0;
-    int32_t* d_lut = nullptr;
-    float2* d_ew = nullptr;
-    float2* d_tw = nullptr;
-    void* d_mf = nullptr;
-    int32_t sym_ew = 0;              // geometry symmetric about the array centre
-    std::string err;
-};

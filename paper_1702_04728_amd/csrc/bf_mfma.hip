@@ -124,7 +124,10 @@ __device__ __forceinline__ void ew_phase(const float2 (&y)[4], const float2 (&W)
     }
 }
 
-template <bool kSym>
+// kSplitV: also carry the E-W output as hi + lo (stage 1 sums hi*hi + lo*hi +
+// hi*lo): every operand then holds ~22 significant bits and the result is
+// FP32-class (max relative power error ~1e-6 against FP64).
+template <bool kSym, bool kSplitV>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bf_mfma_kernel(LaunchArgs a)
 {
@@ -158,7 +161,7 @@ void bf_mfma_kernel(LaunchArgs a)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) W[j][c] = a.ew[((size_t)io.row * kBeamEW + j) * kCyl + c];
+        for (int c = 0; c < 4; ++c) W[j][c] = a.ew[((size_t)io.ew_row * kBeamEW + j) * kCyl + c];
 
     const uint8_t* src = io.in;
     uint2 raw[16];
@@ -178,12 +181,13 @@ void bf_mfma_kernel(LaunchArgs a)
     }
 
     for (int blk = 0; blk < a.n_blk; ++blk) {
-        time_dft_class<false>(wk.s0, raw, s_T, t);
+        time_dft_class(wk.s0, raw, s_T, t);
         __syncthreads();
         if (blk + 1 < a.n_blk) load_block(src + (size_t)(blk + 1) * (kUp * kInputs), raw, t);
 
         // E-W phasing straight into stage-1 A fragments: feeds 16 a + n, a = 4q + ia
         half8 A[4][2];
+        [[maybe_unused]] half8 Alo[4][2];
         if constexpr (kSym) {  // both pols per LDS read
             float2 v[2][4][4];  // [p][j][ia]
 #pragma unroll
@@ -201,7 +205,10 @@ void bf_mfma_kernel(LaunchArgs a)
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) A[j][p] = pack_half8(v[p][j]);
+                for (int j = 0; j < 4; ++j) {
+                    if constexpr (kSplitV) split_half8(v[p][j], A[j][p], Alo[j][p]);
+                    else A[j][p] = pack_half8(v[p][j]);
+                }
         } else {  // one pol at a time keeps the live set within 2 waves/SIMD
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
@@ -217,7 +224,10 @@ void bf_mfma_kernel(LaunchArgs a)
                     ew_phase<kSym>(y, W, v, ia);
                 }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) A[j][p] = pack_half8(v[j]);
+                for (int j = 0; j < 4; ++j) {
+                    if constexpr (kSplitV) split_half8(v[j], A[j][p], Alo[j][p]);
+                    else A[j][p] = pack_half8(v[j]);
+                }
             }
         }
         __syncthreads();
@@ -233,6 +243,7 @@ void bf_mfma_kernel(LaunchArgs a)
                     const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
                     D1[tau] = mfma16(A[j][p], F1h[tau], zero);
                     D1[tau] = mfma16(A[j][p], F1l[tau], D1[tau]);
+                    if constexpr (kSplitV) D1[tau] = mfma16(Alo[j][p], F1h[tau], D1[tau]);
                 }
                 // twiddle in FP32, split into hi + lo B fragments (K = (b, re/im), column c)
                 half8 Bh[2], Bl[2];
@@ -276,7 +287,7 @@ void bf_mfma_kernel(LaunchArgs a)
             for (int i = 0; i < 4; ++i)
                 P[(s2 * 4 + j) * 512 + n + 16 * nu + 32 * (4 * q + i)] = acc[j][nu][i];
     __syncthreads();
-    write_beams(P, nullptr, a.lut + (size_t)io.row * kBeamNS, io.out, wk.s0, t);
+    write_beams(P, a.lut + (size_t)io.row * kBeamNS, io.out, wk.s0, t);
 }
 
 }  // namespace
@@ -286,8 +297,13 @@ hipError_t launch_mfma(const LaunchArgs& a, hipStream_t stream)
     if (a.n_units <= 0) return hipSuccess;
     LaunchArgs args = a;
     void* params[] = {&args};
-    const void* k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true>)
-                             : reinterpret_cast<const void*>(&bf_mfma_kernel<false>);
+    const void* k;
+    if (a.split_v)
+        k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true, true>)
+                     : reinterpret_cast<const void*>(&bf_mfma_kernel<false, true>);
+    else
+        k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true, false>)
+                     : reinterpret_cast<const void*>(&bf_mfma_kernel<false, false>);
     return hipLaunchKernel(k, dev::grid_for(a.n_units), dim3(dev::kThreads), params, 0, stream);
 }
 

@@ -21,7 +21,7 @@
 #include <thread>
 #include <vector>
 
-#include "bf_internal.h"
+#include "bf_plan.h"
 
 namespace {
 
@@ -302,8 +302,9 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     a.n_time = n_time;
     a.max_slots = S;
     a.sym_ew = p->sym_ew;
+    a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
     auto launch = [&](hipStream_t on) {
-        return p->cfg.precision == BF_FP16_MFMA ? bf::launch_mfma(a, on) : bf::launch_fp32(a, on);
+        return p->cfg.precision == BF_FP32_FFT ? bf::launch_fp32(a, on) : bf::launch_mfma(a, on);
     };
     if (d->use_graph) {
         if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)

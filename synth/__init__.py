@@ -87,14 +87,19 @@ def channel_frames(rng: np.random.Generator, freq_hz: float, n_frames: int, sour
                    out: np.ndarray, sigma: float = SIGMA, frame0: int = 0) -> None:
     """Fill out[f][t][i] (u8) for frames frame0 .. frame0+n_frames-1 of one channel.
 
-    Draw order per frame: real noise [384][2048], then imaginary noise.
+    Draw order per frame: real noise [384][2048], then imaginary noise (nothing is
+    drawn when sigma = 0).
     """
     spat = _spatial(freq_hz, sources) if sources else None
     for f in range(n_frames):
-        re = rng.standard_normal((N_TIME, N_INPUTS), dtype=np.float32)
-        im = rng.standard_normal((N_TIME, N_INPUTS), dtype=np.float32)
-        re *= sigma
-        im *= sigma
+        if sigma == 0.0:      # noiseless: nothing drawn (the values would be zeroed)
+            re = np.zeros((N_TIME, N_INPUTS), dtype=np.float32)
+            im = np.zeros((N_TIME, N_INPUTS), dtype=np.float32)
+        else:
+            re = rng.standard_normal((N_TIME, N_INPUTS), dtype=np.float32)
+            im = rng.standard_normal((N_TIME, N_INPUTS), dtype=np.float32)
+            re *= sigma
+            im *= sigma
         if spat is not None:
             t_abs = (frame0 + f) * N_TIME + np.arange(N_TIME, dtype=np.float64)
             sig = _temporal(t_abs, sources) @ spat
@@ -163,6 +168,46 @@ def noise_frames(seed: int, n_frames: int, n_chan: int, sigma: float = SIGMA) ->
         channel_frames(rng, 600e6, n_frames, [], buf, sigma=sigma)
         raw[:, c] = buf
     return raw
+
+
+def drifting_source(seed: int, freqs, n_frames: int, phi0_deg: float = 0.2,
+                    rate_deg: float = 0.3, sin_theta: float = float(np.sin(np.deg2rad(20.0))),
+                    amp: float = 3.0):
+    """Noise plus one point source that moves E-W by rate_deg per frame (tone at
+    the channel centre).  Returns raw u8 [n_frames][n_chan][384][2048] and the
+    source's E-W offset in degrees per frame.  One seeded stream per channel."""
+    freqs = np.atleast_1d(np.asarray(freqs, dtype=np.float64))
+    raw = np.empty((n_frames, len(freqs), N_TIME, N_INPUTS), np.uint8)
+    phi = phi0_deg + rate_deg * np.arange(n_frames)
+    kids = np.random.SeedSequence(seed).spawn(len(freqs))
+    for ci, f in enumerate(freqs):
+        rng = np.random.default_rng(kids[ci])
+        for fr in range(n_frames):
+            channel_frames(rng, float(f), 1, [Source(sin_theta, float(phi[fr]), amp)],
+                           raw[fr:fr + 1, ci], frame0=fr)
+    return raw, phi
+
+
+def point_source_frames(freqs, sin_theta, phi_deg: float = 0.0, amp: float = 6.0) -> np.ndarray:
+    """One noiseless frame per channel slot: slot i at freqs[i] sees one point
+    source at sin_theta[i] (a scalar applies to every slot), E-W offset phi_deg,
+    tone at the channel centre.  Returns u8 [1][n][384][2048]."""
+    freqs = np.atleast_1d(np.asarray(freqs, dtype=np.float64))
+    st = np.broadcast_to(np.asarray(sin_theta, dtype=np.float64), freqs.shape)
+    raw = np.empty((1, len(freqs), N_TIME, N_INPUTS), np.uint8)
+    for i, f in enumerate(freqs):
+        channel_frames(None, float(f), 1, [Source(float(st[i]), phi_deg, amp)], raw[:, i],
+                       sigma=0.0)
+    return raw
+
+
+def tracking_pointings(phi_src_deg, lead_beam: int = 2, spacing_deg: float = 0.4) -> np.ndarray:
+    """E-W directions sin(phi_j) per frame for four beams spaced spacing_deg
+    apart whose beam lead_beam sits on the source offset phi_src_deg[frame]."""
+    phi_src = np.atleast_1d(np.asarray(phi_src_deg, dtype=np.float64))
+    j = np.arange(4)
+    deg = (j[None, :] - lead_beam) * spacing_deg + phi_src[:, None]
+    return np.sin(np.deg2rad(deg))
 
 
 def uniform_bytes(seed: int, shape) -> np.ndarray:

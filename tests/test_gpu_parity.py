@@ -13,8 +13,8 @@ pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
 TOL_FP32 = 1e-5
-TOL = {"fp32": 1e-5, "fp16": 2e-3}
-PRECISIONS = ["fp32", "fp16"]
+TOL = {"fp32": 1e-5, "fp16": 2e-3, "fp32_mfma": 1e-5}
+PRECISIONS = ["fp32", "fp16", "fp32_mfma"]
 C0 = 299_792_458.0
 
 
@@ -84,7 +84,7 @@ def test_other_frame_lengths(torch_mod, bfm, oracle_mod, n_time, precision):
     freqs = np.array([433.2e6, 777.7e6])
     got = _run(torch_mod, bfm, raw, freqs, precision=precision)
     ref = oracle_mod.beamform(oracle_mod.Geometry(n_time=n_time), freqs, raw)
-    if precision == "fp32":
+    if precision != "fp16":
         err = _rel(got, ref)
     else:
         # Short integrations (2 n_time / 16 terms per output) leave some outputs far

@@ -11,7 +11,7 @@ from conftest import gpu_available
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
-TOL = {"fp32": 1e-5, "fp16": 2e-3}
+TOL = {"fp32": 1e-5, "fp16": 2e-3, "fp32_mfma": 1e-5}
 J, L = 1, 2
 
 
@@ -61,7 +61,7 @@ def _stream(torch_mod, bfm, ring, precision, n_frames=10, events=EVENTS, **kw):
     return st, log, out.cpu().numpy()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp32_mfma"])
 def test_stream_outputs_match_batch_and_oracle(torch_mod, bfm, oracle_mod, pool, precision):
     ring = _ring(torch_mod, pool, 4, 6)
     st, log, out = _stream(torch_mod, bfm, ring, precision, use_graph=True)
@@ -83,7 +83,7 @@ def test_stream_outputs_match_batch_and_oracle(torch_mod, bfm, oracle_mod, pool,
     assert checked >= 10
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp32_mfma"])
 @pytest.mark.parametrize("chunk", [128, 16])
 def test_chunked_partial_sums_equal_whole_frames(torch_mod, bfm, pool, precision, chunk):
     ring = _ring(torch_mod, pool, 3, 5)

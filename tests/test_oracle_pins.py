@@ -308,6 +308,36 @@ def test_point_source_peaks_in_predicted_beam(oracle_mod):
     assert out[b, q] > 1000 * np.median(out)
 
 
+def test_tracking_beam_follows_drifting_source(oracle_mod):
+    """Sec. 3.1 (E-W beams static or tracking): a source drifting 0.3 deg E-W per frame
+    stays at the peak of the beam whose direction follows it, while with static beams
+    its power in that beam falls as the closed-form 4-cylinder array factor predicts
+    and the peak moves to the next E-W beam."""
+    f = 600e6
+    raw, phi = synth.drifting_source(51, [f], 3)
+    track = synth.tracking_pointings(phi)
+    m = 171                                   # N-S beam of theta = 20 deg at 600 MHz
+    x = (np.arange(4) - 1.5) * 20.0
+    u_src = np.sin(np.deg2rad(phi))
+    static = oracle_mod.beamform(_geom(oracle_mod), [f], raw)
+    for fr in range(3):
+        tr = oracle_mod.beamform(_geom(oracle_mod, sin_phi_ew=track[fr]), [f], raw[fr:fr + 1])
+        b, q = np.unravel_index(np.argmax(tr[0, 0]), tr[0, 0].shape)
+        assert (b, q) == (2 * 256 + m, 8)
+        af = lambda s: abs(np.exp(2j * np.pi * f * x * (u_src[fr] - s) / C0).sum()) ** 2
+        ratio = static[fr, 0, 2 * 256 + m, 8] / tr[0, 0, 2 * 256 + m, 8]
+        expect = af(math.sin(math.radians(0.2))) / af(track[fr, 2])
+        assert abs(ratio - expect) < 0.02 * max(expect, 0.05)
+    # static beams: the peak E-W beam is the array factor's argmax (at 0.8 deg the
+    # 1.43 deg grating-lobe spacing of 20 m cylinders at 600 MHz favours -0.6 deg)
+    sphi = np.sin(np.deg2rad((np.arange(4) - 1.5) * 0.4))
+    for fr in range(3):
+        af = [abs(np.exp(2j * np.pi * f * x * (u_src[fr] - s) / C0).sum()) for s in sphi]
+        j_pred = int(np.argmax(af))
+        assert int(np.argmax(static[fr, 0, :, 8].reshape(4, 256)[:, m])) == j_pred
+        assert j_pred == [2, 3, 0][fr]
+
+
 def test_alias_lands_where_geometry_says(oracle_mod):
     """Sec. 3.3: above ~490 MHz a source also appears in an aliased beam; a 26 deg
     source at 760 MHz aliases to sin(theta) = sin(26) - c/(f d) (about -59 deg)."""
