@@ -180,6 +180,10 @@ def _bind(lib):
     lib.orc_beamform.restype = ctypes.c_int
     lib.orc_max_threads.argtypes = []
     lib.orc_max_threads.restype = ctypes.c_int
+    lib.orc_rescale_u8.argtypes = [vp, vp, vp, i64, vp]
+    lib.orc_rescale_u8.restype = None
+    lib.orc_group_bins.argtypes = [vp, i64, i32, i32, vp]
+    lib.orc_group_bins.restype = None
     return lib
 
 
@@ -193,6 +197,44 @@ def _cplx(a) -> np.ndarray:
 
 def max_threads() -> int:
     return int(_load().orc_max_threads())
+
+
+def group_bins(fine, group: int) -> np.ndarray:
+    """Sum centre-shifted fine bins (last axis, length L) into L / group coarse
+    sub-channels, each the `group` fine bins nearest its centre."""
+    fine = np.ascontiguousarray(fine, dtype=np.float64)
+    L = fine.shape[-1]
+    if L % group:
+        raise ValueError("group must divide the fine bin count")
+    out = np.empty(fine.shape[:-1] + (L // group,), np.float64)
+    _load().orc_group_bins(_ptr(fine), fine.size // L, L, group, _ptr(out))
+    return out
+
+
+def beamform_upchan128(g: Geometry, freqs, raw, lut_override=None, n_threads: int = 0,
+                       units=None) -> np.ndarray:
+    """The paper's up-channelisation (Sec. 3, Sec. 3.2): 128-point DFTs of every 128
+    samples, Stokes I, integrated over the frame into 16 sub-channels of 8 fine
+    channels each.  Output [.., beams, 16] like beamform."""
+    g128 = Geometry(**{k: getattr(g, k) for k in ("n_feed", "pad", "n_cyl", "n_pol",
+                                                  "n_beam_ns", "n_beam_ew", "n_time",
+                                                  "feed_spacing_m", "c0", "cyl_x_m",
+                                                  "sin_theta_ns", "sin_phi_ew")}, n_dft=128)
+    fine = beamform(g128, freqs, raw, lut_override=lut_override, n_threads=n_threads,
+                    units=units)
+    return group_bins(fine, 8)
+
+
+def rescale_u8(P, scale, offset) -> np.ndarray:
+    """8-bit output codes clamp(rint(P * scale + offset), 0, 255), decided in FP32
+    (Sec. 3, Table 1; the rule is a reading).  P: FP64 powers; scale, offset:
+    broadcast to P's shape and rounded to FP32."""
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    sc = np.ascontiguousarray(np.broadcast_to(np.asarray(scale, np.float32), P.shape))
+    of = np.ascontiguousarray(np.broadcast_to(np.asarray(offset, np.float32), P.shape))
+    out = np.empty(P.shape, np.uint8)
+    _load().orc_rescale_u8(_ptr(P), _ptr(sc), _ptr(of), P.size, _ptr(out))
+    return out
 
 
 def decode(raw) -> np.ndarray:

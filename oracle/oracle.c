@@ -30,6 +30,10 @@
  *            imaginary parts and sum the two polarisations), integrated over
  *            all blocks of the frame (24 blocks of 16 = 384 samples = 0.983 ms,
  *            Table 1).
+ *   8-bit    Sec. 3 and Table 1: the integrated beams are rescaled to 8-bit
+ *            integers (rule not given: an affine rescale per output, decided
+ *            in FP32 like the library, since floating point decides an
+ *            integer there).
  *
  * Conventions the paper leaves open (nibble order, input order, signs,
  * rounding of Eq. (1), sub-channel order) are fixed by the library's
@@ -41,8 +45,8 @@
  *   - E-W weight W[j][c] = exp(-2 pi i f x_c sin(phi_j) / c0);
  *   - output sub-channel q holds DFT bin s = (q + L/2) mod L (centre-shifted),
  *     beam index = j * n_beam_ns + m.
- * All arithmetic is FP64.  Sizes are parameters so that tiny cases can be
- * brute-forced in tests.
+ * All arithmetic is FP64 except the 8-bit code decision.  Sizes are
+ * parameters so that tiny cases can be brute-forced in tests.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -356,6 +360,46 @@ int orc_beamform(const orc_geom *g, const double *freqs, int32_t n_chan,
                                n_units, out, n_threads);
     free(units);
     return r;
+}
+
+/*
+ * The paper's own up-channelisation (Sec. 3, Sec. 3.2): a 128-point DFT of
+ * every 128 samples (3.05 kHz fine channels), squared, then integrated to 16
+ * sub-channels of 24.4 kHz per 0.983 ms.  With the fine powers from
+ * orc_beamform at n_dft = L (centre-shifted fine bin q', summed over blocks and
+ * pols), coarse sub-channel q sums the G fine bins nearest its centre:
+ * q = ((q' + G/2) / G) mod (L/G), i.e. fine bins q' = G q - G/2 .. G q + G/2 - 1
+ * (mod L).  fine = [rows][L], coarse = [rows][L/G].
+ */
+void orc_group_bins(const double *fine, int64_t rows, int32_t L, int32_t G, double *coarse)
+{
+    const int32_t nq = L / G;
+    for (int64_t r = 0; r < rows; ++r) {
+        for (int32_t q = 0; q < nq; ++q) coarse[r * nq + q] = 0.0;
+        for (int32_t qf = 0; qf < L; ++qf) {
+            int32_t q = ((qf + G / 2) / G) % nq;
+            coarse[r * nq + q] += fine[r * L + qf];
+        }
+    }
+}
+
+/*
+ * 8-bit output (Sec. 3, Table 1: the integrated beams are rescaled to 8-bit
+ * integers; the paper gives no rule).  Reading: an affine rescale per output,
+ * code = clamp(rint(P * scale + offset), 0, 255).  The code is an integer
+ * decided by floating point, so it is decided in the library's precision:
+ * P rounded to FP32, one FP32 fused multiply-add, rint (round half to even).
+ * A NaN argument gives code 0.
+ */
+void orc_rescale_u8(const double *P, const float *scale, const float *offset, int64_t n,
+                    uint8_t *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        float x = rintf(fmaf((float)P[i], scale[i], offset[i]));
+        if (!(x >= 0.0f)) x = 0.0f;
+        if (x > 255.0f) x = 255.0f;
+        out[i] = (uint8_t)x;
+    }
 }
 
 int orc_max_threads(void)

@@ -51,6 +51,13 @@ MUTANTS = [
      "            for (int32_t p = 0; p < 1; ++p)\n                for (int32_t blk"),
     ("input index feed-major",
      "int64_t i = ((int64_t)c * NF + n) * NP + p;", "int64_t i = ((int64_t)c * NP + p) * NF + n;"),
+    ("8-bit code truncated instead of rounded",
+     "float x = rintf(fmaf((float)P[i], scale[i], offset[i]));",
+     "float x = truncf(fmaf((float)P[i], scale[i], offset[i]));"),
+    ("8-bit code saturating at 254",
+     "if (x > 255.0f) x = 255.0f;", "if (x > 254.0f) x = 254.0f;"),
+    ("fine bins grouped without centring",
+     "int32_t q = ((qf + G / 2) / G) % nq;", "int32_t q = (qf / G) % nq;"),
     ("beam index N-S major",
      "out[((size_t)j * NM + m) * L + q] +=", "out[((size_t)m * NJ + j) * L + q] +="),
 ]

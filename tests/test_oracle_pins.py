@@ -388,3 +388,56 @@ def test_dispersed_pulse_sweeps_down_in_subchannel(oracle_mod):
     beam = int(np.argmax(out[k, 0].sum(axis=1)))
     g = oracle_mod.Geometry()
     assert abs(g.sin_theta_ns[beam % 256] - 0.3) < 3 / 128
+
+
+# ---------------------------------------------------------------- 8-bit output
+def test_rescale_u8_definition(oracle_mod):
+    """Sec. 3 and Table 1 put the output in 8-bit integers without a rule; the reading is
+    code = clamp(rint(P scale + offset), 0, 255) decided in FP32.  Pinned by ties (round
+    half to even), saturation at both ends, NaN, and an independent float32 evaluation
+    on seeded values (product exact in float64, one rounding to float32)."""
+    P = np.array([2.5, 3.5, -0.5, 0.5, 1.5, 254.5, 255.5, 1e30, -1e30, np.nan, 0.49999997])
+    assert oracle_mod.rescale_u8(P, 1.0, 0.0).tolist() == [2, 4, 0, 0, 2, 254, 255, 255, 0, 0, 0]
+    assert oracle_mod.rescale_u8([10.0], 0.0, 7.0).tolist() == [7]
+    rng = np.random.default_rng(81)
+    P = rng.uniform(0, 4e7, 20000)
+    sc = rng.uniform(2e-6, 1e-5, P.size).astype(np.float32)
+    of = rng.uniform(-40, 40, P.size).astype(np.float32)
+    t = (np.float32(P).astype(np.float64) * sc.astype(np.float64) + of.astype(np.float64))
+    t32 = t.astype(np.float32)
+    ref = np.clip(np.rint(t32), 0, 255).astype(np.uint8)
+    got = oracle_mod.rescale_u8(P, sc, of)
+    assert 0 < (ref == 0).sum() and 0 < (ref == 255).sum()
+    assert np.array_equal(got, ref)
+
+
+# ---------------------------------------------------------------- 128-point up-channelisation
+def test_group_bins_brute_force(oracle_mod):
+    """Coarse sub-channel q sums the 8 centre-shifted fine bins 8q - 4 .. 8q + 3 (mod 128)."""
+    fine = np.random.default_rng(5).uniform(0, 1, (3, 7, 128))
+    ref = np.roll(fine, 4, axis=-1).reshape(3, 7, 16, 8).sum(-1)
+    assert np.allclose(oracle_mod.group_bins(fine, 8), ref, rtol=1e-15, atol=0)
+    one = np.zeros(128)
+    for qf in range(128):
+        one[:] = 0
+        one[qf] = 1
+        assert int(np.argmax(oracle_mod.group_bins(one, 8))) == ((qf + 4) // 8) % 16
+
+
+def test_upchan128_dc_tone_and_parseval(oracle_mod):
+    """Sec. 3 and Sec. 3.2: 128-point DFTs of 128-sample blocks, integrated to 16 sub-
+    channels.  A tone at the channel centre (constant integer samples, so exact) puts
+    everything in sub-channel 8 with 3 x 128^2 / (24 x 16^2) = 8 times the 16-point
+    power; for any input the total over sub-channels is 8 times the 16-point total
+    (Parseval: L sum |x|^2 per block)."""
+    g = _geom(oracle_mod)
+    raw = np.empty((1, 1, 384, 2048), np.uint8)
+    synth.channel_frames(None, 600e6, 1, [synth.Source(0.3, 0.2, 3.0)], raw[:, 0], sigma=0.0)
+    o16 = oracle_mod.beamform(g, [600e6], raw)[0, 0]
+    o128 = oracle_mod.beamform_upchan128(g, [600e6], raw)[0, 0]
+    assert np.allclose(o128[:, 8], 8 * o16[:, 8], rtol=1e-12, atol=0)
+    assert np.abs(np.delete(o128, 8, axis=1)).max() < 1e-9 * o128.max()
+    rnd = synth.uniform_bytes(6, (1, 1, 384, 2048))
+    t16 = oracle_mod.beamform(g, [450e6], rnd)[0, 0].sum(axis=1)
+    t128 = oracle_mod.beamform_upchan128(g, [450e6], rnd)[0, 0].sum(axis=1)
+    assert np.allclose(t128, 8 * t16, rtol=1e-12, atol=0)
