@@ -28,6 +28,9 @@ sys.path.insert(0, ROOT)
 METRIC = "frequency channels sustained in real time, FP32 vs FP16-MFMA; p99 frame latency"
 FRAME_S = 384 * 2.56e-6                 # 0.98304 ms
 BYTES_PER_UNIT = 384 * 2048 + 1024 * 16 * 4  # 851,968 algorithmic HBM bytes per channel-frame
+# 128-point up-channelisation: kept beams of 24 sample phases x 16 sub-channels x
+# 8 lines x 256 N-S beams, complex FP32, between the two passes
+FINE_BYTES_PER_UNIT = 24 * 16 * 8 * 256 * 8
 # Conventional flop count per sample (5 N log2 N FFTs): N-S 8 x 512-point = 184,320,
 # E-W 1024 beams x 2 pols x 4 complex MACs = 65,536, 2048 16-point DFTs = 40,960,
 # detection 8,192.  Times 384 samples per channel-frame.
@@ -114,15 +117,23 @@ def copy_probe(torch, mib: int, reps: int):
     log("copy probe: %d x %d MiB" % (reps, mib))
 
 
-def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None):
+def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None, u8=None, upchan=16):
     """Warm up, then time args.steps launches of one path on the current stream.
-    sin_phi: per-frame E-W directions (tracking beams), or None for static beams."""
+    sin_phi: per-frame E-W directions (tracking beams), or None for static beams;
+    u8: (scale, offset) tables for 8-bit output, or None for FP32 output."""
     beam = bf.Beamformer(freqs, precision=prec)
     n_frames = raw.shape[0]
-    out = torch.empty(beam.out_shape(n_frames), dtype=torch.float32, device=raw.device)
+    out = torch.empty(beam.out_shape(n_frames), dtype=torch.uint8 if u8 else torch.float32,
+                      device=raw.device)
+
+    def launch():
+        if u8:
+            beam.frame_u8(raw, u8[0], u8[1], out)
+        else:
+            beam.frame(raw, out, sin_phi_ew=sin_phi, upchan=upchan)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
-        beam.frame(raw, out, sin_phi_ew=sin_phi)
+        launch()
     torch.cuda.synchronize()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -132,7 +143,7 @@ def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None):
     ev0.record(stream)
     for i in range(args.steps):
         starts[i].record(stream)
-        beam.frame(raw, out, sin_phi_ew=sin_phi)
+        launch()
         ends[i].record(stream)
     ev1.record(stream)
     torch.cuda.synchronize()
@@ -141,7 +152,11 @@ def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None):
     ms_step = total_ms / args.steps
     beam.close()
     log("%s%s: timed %d steps: %.4f ms/step (events)"
-        % (prec, "" if sin_phi is None else " tracking", args.steps, ms_step))
+        % (prec, " tracking" if sin_phi is not None else " u8" if u8 else
+           " upchan128" if upchan == 128 else "", args.steps, ms_step))
+    unit_bytes = BYTES_PER_UNIT - (3 * 65536 // 4 if u8 else 0)
+    if upchan == 128:  # the first pass's beams, written once and read once
+        unit_bytes += 2 * FINE_BYTES_PER_UNIT
     kern_s = float(np.mean(per)) * 1e-3
     flops = FLOPS_PER_UNIT[prec] * units
     peak, punit, bound = PEAK[prec]
@@ -152,13 +167,14 @@ def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None):
         "dtype": DTYPE[prec],
         "roofline": {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
                      "unit": punit, "frac": round(achieved / peak, 4),
-                     "traffic": traffic_from_profiles(prec, units) if sin_phi is None else None,
+                     "traffic": (traffic_from_profiles(prec, units)
+                                 if sin_phi is None and not u8 and upchan == 16 else None),
                      "kernel": (KERNEL_NAME if sin_phi is None else KERNEL_NAME_GENERAL)[prec],
                      "flops_per_launch": flops},
-        "hbm": {"achieved_GBs": round(BYTES_PER_UNIT * units / kern_s / 1e9, 1),
+        "hbm": {"achieved_GBs": round(unit_bytes * units / kern_s / 1e9, 1),
                 "peak_GBs": HBM_PEAK_GBS,
-                "frac": round(BYTES_PER_UNIT * units / kern_s / 1e9 / HBM_PEAK_GBS, 4),
-                "bytes_per_launch": BYTES_PER_UNIT * units},
+                "frac": round(unit_bytes * units / kern_s / 1e9 / HBM_PEAK_GBS, 4),
+                "bytes_per_launch": unit_bytes * units},
         "input_GBs": round(raw.numel() / (ms_step * 1e-3) / 1e9, 1),
         "step_ms_p50": round(float(np.percentile(per, 50)), 5),
         "step_ms_p99": round(float(np.percentile(per, 99)), 5),
@@ -254,6 +270,9 @@ def main():
                     help="skip the tracking E-W beam measurement")
     ap.add_argument("--no-fullband", action="store_true",
                     help="skip the 1024-channel measurement")
+    ap.add_argument("--no-u8", action="store_true", help="skip the 8-bit output measurement")
+    ap.add_argument("--no-upchan128", action="store_true",
+                    help="skip the 128-point up-channelisation measurement")
     ap.add_argument("--serve-frames", type=int, default=10000,
                     help="frames of the paced serving loop per path (0 skips it)")
     ap.add_argument("--sweep", action="store_true",
@@ -301,6 +320,19 @@ def main():
         for prec in paths:
             results[prec]["tracking"] = time_path(torch, bf, prec, raw, freqs, units, args,
                                                   sin_phi=track)
+    if not args.no_u8:
+        # 8-bit output: noise mean (9.874e6 at sigma 2.5) maps to code 64
+        tab = (len(freqs), 1024, 16)
+        scale = torch.full(tab, 64.0 / 9.874e6, dtype=torch.float32, device=dev)
+        offset = torch.zeros(tab, dtype=torch.float32, device=dev)
+        for prec in paths:
+            results[prec]["u8"] = time_path(torch, bf, prec, raw, freqs, units, args,
+                                            u8=(scale, offset))
+    if not args.no_upchan128 and "fp32" in paths:
+        # the paper's 128-point up-channelisation (two passes), FP32 path; flops as
+        # the 16-point path plus 16 twiddles and 8-point DFTs per beam and block
+        results["fp32"]["upchan128"] = time_path(torch, bf, "fp32", raw, freqs, units, args,
+                                                 upchan=128)
     if not args.no_fullband:
         # all 1024 channels of the band (400-800 MHz), two frames per launch: the
         # workload's bytes tiled over the band, each channel with its own tables

@@ -121,6 +121,38 @@ int32_t beamform_init(const bf_config *cfg, const double *chan_freq_hz, int32_t 
 int32_t beamform_frame(bf_plan *plan, const uint8_t *d_in, int32_t n_frames, float *d_out,
                        void *stream);
 
+/* The paper's own up-channelisation (Sec. 3: fine channelisation by 128 times
+ * to 3 kHz, Stokes I integrated to 16 sub-channels of 24.4 kHz per 0.983 ms;
+ * Sec. 3.2: every 128 samples transformed).  As beamform_frame, with the
+ * 16-point DFT of 16-sample blocks replaced by a 128-point DFT of each
+ * 128-sample block: fine bin s' (centre-shifted q' = (s' + 64) mod 128) is
+ * squared and summed over both pols and the frame's blocks into sub-channel
+ * q = ((q' + 4) / 8) mod 16, the 8 fine channels nearest its centre.
+ * Two passes: the beamforming kernel writes every kept beam of every (sample
+ * phase, sub-channel) to a plan-owned workspace (6.3 MB per channel-frame,
+ * allocated at the first call, about 256 channel-frames or one frame at a
+ * time), the second kernel completes the 128-point transforms and integrates.
+ *   d_in, d_out: as beamform_frame (d_out fully overwritten).
+ * Needs n_time % 128 == 0 and a BF_FP32_FFT plan (else BF_E_UNSUPPORTED);
+ * BF_E_NOMEM if the workspace cannot be allocated. */
+int32_t beamform_frame_upchan128(bf_plan *plan, const uint8_t *d_in, int32_t n_frames,
+                                 float *d_out, void *stream);
+
+/* 8-bit output (Sec. 3 and Table 1: the integrated Stokes I beams leave the
+ * beamformer rescaled to 8-bit integers; the rule is not given, this is an
+ * affine rescale per channel, beam and sub-channel).  As beamform_frame, but
+ * each integrated power P (FP32, as beamform_frame computes it) is written as
+ *   code = min(255, max(0, rint(fmaf(P, scale, offset))))
+ * in FP32, rint rounding half to even.
+ *   d_scale, d_offset: device f32 [n_chan][1024][16], caller-owned, read only;
+ *   d_out: device u8 [n_frames][n_chan][1024][16], 16-byte aligned, fully
+ *          overwritten (a quarter of beamform_frame's output bytes).
+ * n_frames = 0 is a valid no-op.  Errors: BF_E_INVAL for NULL or misaligned
+ * buffers. */
+int32_t beamform_frame_u8(bf_plan *plan, const uint8_t *d_in, int32_t n_frames,
+                          const float *d_scale, const float *d_offset, uint8_t *d_out,
+                          void *stream);
+
 /* Tracking E-W beams (Sec. 3.1: the E-W beams may be static or tracking).  As
  * beamform_frame, with the E-W directions given per frame instead of the
  * plan's static ones:

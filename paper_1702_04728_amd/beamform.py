@@ -29,7 +29,8 @@ N_BEAM_NS = 256
 # Every symbol include/beamform.h declares.
 EXPORTED = (
     "beamform_default_config", "beamform_compute_lut", "beamform_init", "beamform_frame",
-    "beamform_frame_tracking", "beamform_stream", "beamform_stream_schedule", "beamform_get_lut", "beamform_plan_info",
+    "beamform_frame_upchan128", "beamform_frame_u8", "beamform_frame_tracking",
+    "beamform_stream", "beamform_stream_schedule", "beamform_get_lut", "beamform_plan_info",
     "beamform_destroy", "beamform_strerror", "beamform_last_error",
 )
 
@@ -148,6 +149,8 @@ def load_library():
         "beamform_init": ([cp, vp, i32, vp, ctypes.POINTER(vp)], i32),
         "beamform_frame": ([vp, vp, i32, vp, vp], i32),
         "beamform_frame_tracking": ([vp, vp, i32, vp, vp, vp], i32),
+        "beamform_frame_u8": ([vp, vp, i32, vp, vp, vp, vp], i32),
+        "beamform_frame_upchan128": ([vp, vp, i32, vp, vp], i32),
         "beamform_stream": ([vp, ctypes.POINTER(BfStreamDesc), ctypes.POINTER(BfStreamStats), vp],
                             i32),
         "beamform_stream_schedule": ([ctypes.POINTER(BfStreamDesc), ctypes.c_int64,
@@ -267,10 +270,12 @@ class Beamformer:
     def out_shape(self, n_frames: int):
         return (n_frames, self.n_chan, N_BEAMS, N_UPCHAN)
 
-    def frame(self, raw, out=None, stream=None, sin_phi_ew=None):
+    def frame(self, raw, out=None, stream=None, sin_phi_ew=None, upchan=16):
         """Beamform raw [n_frames][n_chan][n_time][2048] (CUDA uint8) into out
         [n_frames][n_chan][1024][16] (CUDA float32).  sin_phi_ew: None for the plan's
-        static E-W beams, or [n_frames][4] E-W directions per frame (tracking beams)."""
+        static E-W beams, or [n_frames][4] E-W directions per frame (tracking beams).
+        upchan: 16 (16-point DFT of 16-sample blocks) or 128 (the 128-point
+        up-channelisation integrated to the same 16 sub-channels)."""
         import torch
         if self._plan is None:
             raise BeamformError(-4, "plan destroyed")
@@ -288,7 +293,15 @@ class Beamformer:
                 and out.is_contiguous() and tuple(out.shape) == self.out_shape(n_frames)):
             raise ValueError("out must be a contiguous CUDA float32 tensor of shape %s"
                              % (self.out_shape(n_frames),))
-        if sin_phi_ew is None:
+        if upchan not in (16, 128):
+            raise ValueError("upchan must be 16 or 128")
+        if upchan == 128:
+            if sin_phi_ew is not None:
+                raise ValueError("tracking beams use the 16-point up-channelisation")
+            st = self.lib.beamform_frame_upchan128(self._plan, ctypes.c_void_p(raw.data_ptr()),
+                                                   n_frames, ctypes.c_void_p(out.data_ptr()),
+                                                   _stream_handle(stream))
+        elif sin_phi_ew is None:
             st = self.lib.beamform_frame(self._plan, ctypes.c_void_p(raw.data_ptr()), n_frames,
                                          ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
         else:
@@ -299,6 +312,38 @@ class Beamformer:
                 self._plan, ctypes.c_void_p(raw.data_ptr()), n_frames,
                 ctypes.c_void_p(phi.ctypes.data), ctypes.c_void_p(out.data_ptr()),
                 _stream_handle(stream))
+        _check(st, self._plan)
+        return out
+
+    def frame_u8(self, raw, scale, offset, out=None, stream=None):
+        """8-bit output: code = clamp(rint(P * scale + offset), 0, 255) per output,
+        scale/offset CUDA float32 [n_chan][1024][16]; returns CUDA uint8
+        [n_frames][n_chan][1024][16]."""
+        import torch
+        if self._plan is None:
+            raise BeamformError(-4, "plan destroyed")
+        if not (isinstance(raw, torch.Tensor) and raw.is_cuda and raw.dtype == torch.uint8
+                and raw.is_contiguous() and raw.dim() == 4
+                and raw.shape[1:] == (self.n_chan, self.n_time, N_INPUTS)):
+            raise ValueError("raw must be a contiguous CUDA uint8 [n_frames][%d][%d][%d]"
+                             % (self.n_chan, self.n_time, N_INPUTS))
+        tab = (self.n_chan, N_BEAMS, N_UPCHAN)
+        for name, x in (("scale", scale), ("offset", offset)):
+            if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32
+                    and x.is_contiguous() and tuple(x.shape) == tab):
+                raise ValueError("%s must be a contiguous CUDA float32 tensor of shape %s"
+                                 % (name, tab))
+        n_frames = int(raw.shape[0])
+        shape = self.out_shape(n_frames)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.uint8, device=raw.device)
+        if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.uint8
+                and out.is_contiguous() and tuple(out.shape) == shape):
+            raise ValueError("out must be a contiguous CUDA uint8 tensor of shape %s" % (shape,))
+        st = self.lib.beamform_frame_u8(self._plan, ctypes.c_void_p(raw.data_ptr()), n_frames,
+                                        ctypes.c_void_p(scale.data_ptr()),
+                                        ctypes.c_void_p(offset.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
         _check(st, self._plan)
         return out
 

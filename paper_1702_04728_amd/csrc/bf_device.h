@@ -118,6 +118,7 @@ struct UnitIO {
     float* partial;  // this workgroup's partial sums (stream mode), else nullptr
     int row;         // row of the bin table (and of the static E-W weights)
     int ew_row;      // row of the E-W weights
+    uint8_t* out_u8; // 8-bit output of this unit, or nullptr (FP32 output)
     bool first, last;
 };
 // False when the workgroup has no unit (uniform across the workgroup).
@@ -130,6 +131,7 @@ __device__ __forceinline__ bool resolve_unit(const LaunchArgs& a, const Work& wk
         io.partial = nullptr;
         io.row = wk.unit % a.n_chan;
         io.ew_row = a.ew_by_unit ? wk.unit : io.row;
+        io.out_u8 = a.out_u8 ? a.out_u8 + (size_t)wk.unit * kOutPerUnit : nullptr;
         io.first = io.last = true;
         return true;
     }
@@ -142,6 +144,7 @@ __device__ __forceinline__ bool resolve_unit(const LaunchArgs& a, const Work& wk
     io.partial = a.partial + ((size_t)slot * 4 + wk.s0) * kPartialPerWg;
     io.row = slot;
     io.ew_row = slot;
+    io.out_u8 = nullptr;
     io.first = chunk == 0;
     io.last = chunk == a.st->n_chunks - 1;
     return true;
@@ -241,13 +244,45 @@ __device__ __forceinline__ void time_dft_class(int s0, const uint2 (&raw)[16], f
     }
 }
 
-// Raw samples of one 16-sample block: thread t reads bytes 8t .. 8t+7 of
-// each sample (64 lanes x 8 B contiguous per sample).
-__device__ __forceinline__ void load_block(const uint8_t* __restrict__ blk, uint2 (&raw)[16], int t)
+// Raw samples of one block of 16: thread t reads bytes 8t .. 8t+7 of each
+// sample (64 lanes x 8 B contiguous per sample); rows `stride` bytes apart.
+__device__ __forceinline__ void load_block(const uint8_t* __restrict__ blk, uint2 (&raw)[16], int t,
+                                           int stride = kInputs)
 {
 #pragma unroll
     for (int tau = 0; tau < 16; ++tau)
-        raw[tau] = *reinterpret_cast<const uint2*>(blk + tau * kInputs + 8 * t);
+        raw[tau] = *reinterpret_cast<const uint2*>(blk + tau * stride + 8 * t);
+}
+
+// Samples of block iteration `it`: 16 consecutive samples, or (kFine, the
+// first pass of the 128-point up-channelisation) the samples u + 8 tau of
+// 128-sample block it / 8 with u = it % 8, so that the 16-point time DFT is
+// the first step of a 128-point DFT split as 128 = 16 (tau) x 8 (u).
+template <bool kFine>
+__device__ __forceinline__ const uint8_t* block_base(const uint8_t* in, int it)
+{
+    if constexpr (kFine) return in + (size_t)((it >> 3) * 128 + (it & 7)) * kInputs;
+    else return in + (size_t)it * (kUp * kInputs);
+}
+template <bool kFine>
+__device__ __forceinline__ int block_stride()
+{
+    return kFine ? 8 * kInputs : kInputs;
+}
+
+// First pass of the 128-point up-channelisation: the 512 bins of one line
+// (sub-channel k, line p * 4 + j, block iteration it) sit in LDS at bins[];
+// the kept beam of every N-S pointing m is bins[lut[m]].  Lanes `lane` of
+// `n_lanes` write consecutive m.
+__device__ __forceinline__ void write_fine_line(const float2* __restrict__ bins,
+                                                const int32_t* __restrict__ lut,
+                                                float2* __restrict__ dst, int lane, int n_lanes)
+{
+    for (int m = lane; m < kBeamNS; m += n_lanes) dst[m] = bins[lut[m]];
+}
+__device__ __forceinline__ float2* fine_line_ptr(const LaunchArgs& a, int unit, int it, int k, int line)
+{
+    return a.fine + ((((size_t)unit * a.n_blk + it) * 16 + k) * 8 + line) * kBeamNS;
 }
 
 // End of frame: P[(s2 * 4 + j) * 512 + k] holds the integrated power of FFT
@@ -265,6 +300,39 @@ __device__ __forceinline__ void write_beams(const float* __restrict__ P,
         const int ss2 = (q2 + 2) & 3;  // q = s0 + 4 q2 holds s = s0 + 4 ss2
         dst[beam * kUp + s0 + 4 * q2] = P[(ss2 * 4 + jj) * 512 + lut[m]];
     }
+}
+
+// 8-bit output of the same gather: code = clamp(rint(P scale + offset), 0, 255)
+// in FP32 (one fused multiply-add, rint rounds half to even); scale and
+// offset are this channel's [1024][16] rows.
+__device__ __forceinline__ void write_beams_u8(const float* __restrict__ P,
+                                               const int32_t* __restrict__ lut,
+                                               const float* __restrict__ scale,
+                                               const float* __restrict__ offset,
+                                               uint8_t* __restrict__ dst, int s0, int t)
+{
+#pragma unroll 4
+    for (int it = 0; it < 16; ++it) {
+        const int u = it * kThreads + t;
+        const int beam = u >> 2, q2 = u & 3;
+        const int jj = beam >> 8, m = beam & 255;
+        const int ss2 = (q2 + 2) & 3;
+        const int o = beam * kUp + s0 + 4 * q2;
+        const float x = rintf(fmaf(P[(ss2 * 4 + jj) * 512 + lut[m]], scale[o], offset[o]));
+        dst[o] = (uint8_t)fminf(fmaxf(x, 0.f), 255.f);
+    }
+}
+
+// End-of-frame output in the format the launch asks for.
+__device__ __forceinline__ void write_output(const float* P, const LaunchArgs& a, const UnitIO& io,
+                                             int s0, int t)
+{
+    const int32_t* lut = a.lut + (size_t)io.row * kBeamNS;
+    if (io.out_u8)
+        write_beams_u8(P, lut, a.scale + (size_t)io.row * kOutPerUnit,
+                       a.offset + (size_t)io.row * kOutPerUnit, io.out_u8, s0, t);
+    else
+        write_beams(P, lut, io.out, s0, t);
 }
 
 }  // namespace dev

@@ -76,11 +76,16 @@ __device__ __forceinline__ void fft16(float2 (&v)[16])
 
 // Zero-padded 512-point N-S transform of one line held as x[a] = line[16 a + b]
 // by lane b of a 16-lane group; accumulates |X_k|^2 for k = 2 b + r + 32 d into
-// acc[r][d].  bufE / bufO: this group's two transpose buffers.
+// acc[r][d].  bufE / bufO: this group's two transpose buffers (adjacent).
+// kFine: instead, the kept beams of the line go to fine_dst (first pass of the
+// 128-point up-channelisation), gathered through the transpose buffers.
+template <bool kFine>
 __device__ __forceinline__ void ns_line_power(const float2 (&x)[16], float (&acc)[2][16],
                                               float2* __restrict__ bufE,
                                               float2* __restrict__ bufO,
-                                              const float2* __restrict__ tw, int b)
+                                              const float2* __restrict__ tw, int b,
+                                              const int32_t* __restrict__ lut = nullptr,
+                                              float2* __restrict__ fine_dst = nullptr)
 {
     float2 E[16], O[16];
 #pragma unroll
@@ -120,13 +125,27 @@ __device__ __forceinline__ void ns_line_power(const float2 (&x)[16], float (&acc
     // step 3b: 16-point FFT over b gives X[c + 32 d] for c = 2 b (E) and 2 b + 1 (O)
     fft16(E);
     fft16(O);
+    if constexpr (kFine) {
+        float2* bins = bufE;  // 512 bins fit in the group's two buffers
 #pragma unroll
-    for (int d = 0; d < 16; ++d) {
-        acc[0][d] = fmaf(E[d].x, E[d].x, fmaf(E[d].y, E[d].y, acc[0][d]));
-        acc[1][d] = fmaf(O[d].x, O[d].x, fmaf(O[d].y, O[d].y, acc[1][d]));
+        for (int d = 0; d < 16; ++d) {
+            bins[2 * b + 32 * d] = E[d];
+            bins[2 * b + 1 + 32 * d] = O[d];
+        }
+        wave_lds_sync();
+        write_fine_line(bins, lut, fine_dst, b, 16);
+        wave_lds_sync();
+    } else {
+#pragma unroll
+        for (int d = 0; d < 16; ++d) {
+            acc[0][d] = fmaf(E[d].x, E[d].x, fmaf(E[d].y, E[d].y, acc[0][d]));
+            acc[1][d] = fmaf(O[d].x, O[d].x, fmaf(O[d].y, O[d].y, acc[1][d]));
+        }
     }
 }
+static_assert(2 * kXpBuf >= 512, "a group's transpose buffers must hold one line's bins");
 
+template <bool kFine>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bf_fp32_kernel(LaunchArgs a)
 {
@@ -152,7 +171,7 @@ void bf_fp32_kernel(LaunchArgs a)
     float2* bufO = bufE + kXpBuf;
 
     uint2 raw[16];
-    load_block(src, raw, t);
+    load_block(block_base<kFine>(src, 0), raw, t, block_stride<kFine>());
 
     float acc[2][16];
     constexpr int kAcc = sizeof(acc) / sizeof(float);
@@ -168,7 +187,7 @@ void bf_fp32_kernel(LaunchArgs a)
         time_dft_class(wk.s0, raw, T, t);
         __syncthreads();
         // prefetch the next block's samples while the transforms run
-        if (blk + 1 < a.n_blk) load_block(src + (size_t)(blk + 1) * (kUp * kInputs), raw, t);
+        if (blk + 1 < a.n_blk) load_block(block_base<kFine>(src, blk + 1), raw, t, block_stride<kFine>());
         // B1: E-W phasing while loading this group's two lines (feeds 16 a + b)
         float2 v0[16], v1[16];
 #pragma unroll
@@ -185,10 +204,18 @@ void bf_fp32_kernel(LaunchArgs a)
         }
         __syncthreads();
         // B2: N-S transform of both polarisations, power into per-bin accumulators
-        ns_line_power(v0, acc, bufE, bufO, s_tw, b);
-        ns_line_power(v1, acc, bufE, bufO, s_tw, b);
+        if constexpr (kFine) {
+            const int32_t* lut = a.lut + (size_t)io.row * kBeamNS;
+            const int k = wk.s0 + 4 * s2;
+            ns_line_power<true>(v0, acc, bufE, bufO, s_tw, b, lut, fine_line_ptr(a, wk.unit, blk, k, j));
+            ns_line_power<true>(v1, acc, bufE, bufO, s_tw, b, lut, fine_line_ptr(a, wk.unit, blk, k, 4 + j));
+        } else {
+            ns_line_power<false>(v0, acc, bufE, bufO, s_tw, b);
+            ns_line_power<false>(v1, acc, bufE, bufO, s_tw, b);
+        }
         __syncthreads();
     }
+    if constexpr (kFine) return;  // the second pass detects and integrates
 
     if (!io.last) {  // frame continues in the next chunk's launch
         store_partial<kAcc>(&acc[0][0], io.partial, t);
@@ -202,7 +229,7 @@ void bf_fp32_kernel(LaunchArgs a)
         P[g * 512 + 2 * b + 1 + 32 * d] = acc[1][d];
     }
     __syncthreads();
-    write_beams(P, a.lut + (size_t)io.row * kBeamNS, io.out, wk.s0, t);
+    write_output(P, a, io, wk.s0, t);
 }
 
 }  // namespace
@@ -212,8 +239,9 @@ hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream)
     if (a.n_units <= 0) return hipSuccess;
     LaunchArgs args = a;
     void* params[] = {&args};
-    return hipLaunchKernel(reinterpret_cast<const void*>(&bf_fp32_kernel), dev::grid_for(a.n_units),
-                           dim3(dev::kThreads), params, 0, stream);
+    const void* k = a.fine ? reinterpret_cast<const void*>(&bf_fp32_kernel<true>)
+                           : reinterpret_cast<const void*>(&bf_fp32_kernel<false>);
+    return hipLaunchKernel(k, dev::grid_for(a.n_units), dim3(dev::kThreads), params, 0, stream);
 }
 
 }  // namespace bf

@@ -12,6 +12,7 @@
 //                 exp(-2 pi i ((b c) mod 512) / 512), c < 32, b < 16.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -132,7 +133,9 @@ bool mirror_symmetric(const double* cyl_x, const double* sin_phi)
 
 // Checks shared by the batch entry points, then one launch over all units.
 int32_t launch_batch(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float* d_out,
-                     hipStream_t stream, const float2* ew, int32_t ew_by_unit, int32_t sym)
+                     hipStream_t stream, const float2* ew, int32_t ew_by_unit, int32_t sym,
+                     uint8_t* d_out_u8 = nullptr, const float* scale = nullptr,
+                     const float* offset = nullptr)
 {
     bf::LaunchArgs a{};
     a.in = d_in;
@@ -150,13 +153,16 @@ int32_t launch_batch(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float* d
     a.sym_ew = sym;
     a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
     a.ew_by_unit = ew_by_unit;
+    a.out_u8 = d_out_u8;
+    a.scale = scale;
+    a.offset = offset;
     hipError_t e = p->cfg.precision == BF_FP32_FFT ? bf::launch_fp32(a, stream)
                                                    : bf::launch_mfma(a, stream);
     if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
     return BF_OK;
 }
 
-int32_t check_batch(bf_plan* p, const uint8_t* d_in, int32_t n_frames, const float* d_out)
+int32_t check_batch(bf_plan* p, const uint8_t* d_in, int32_t n_frames, const void* d_out)
 {
     if (n_frames < 0) return fail(p, BF_E_INVAL, "n_frames < 0");
     if (n_frames == 0) return BF_OK;
@@ -351,6 +357,90 @@ int32_t beamform_frame(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float*
     return launch_batch(p, d_in, n_frames, d_out, (hipStream_t)stream, p->d_ew, 0, p->sym_ew);
 }
 
+int32_t beamform_frame_u8(bf_plan* p, const uint8_t* d_in, int32_t n_frames,
+                          const float* d_scale, const float* d_offset, uint8_t* d_out,
+                          void* stream)
+{
+    if (!p) return BF_E_INVAL;
+    p->err.clear();
+    int32_t st = check_batch(p, d_in, n_frames, d_out);
+    if (st != BF_OK || n_frames == 0) return st;
+    if (!d_scale || !d_offset) return fail(p, BF_E_INVAL, "NULL scale or offset table");
+    if (((uintptr_t)d_scale & 3) || ((uintptr_t)d_offset & 3))
+        return fail(p, BF_E_INVAL, "scale and offset tables must be 4-byte aligned");
+    return launch_batch(p, d_in, n_frames, nullptr, (hipStream_t)stream, p->d_ew, 0, p->sym_ew,
+                        d_out, d_scale, d_offset);
+}
+
+int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float* d_out,
+                                 void* stream)
+{
+    if (!p) return BF_E_INVAL;
+    p->err.clear();
+    int32_t st = check_batch(p, d_in, n_frames, d_out);
+    if (st != BF_OK || n_frames == 0) return st;
+    if (p->cfg.n_time % 128 != 0)
+        return fail(p, BF_E_UNSUPPORTED, "the 128-point up-channelisation needs n_time % 128 == 0");
+    if (p->cfg.precision != BF_FP32_FFT)
+        return fail(p, BF_E_UNSUPPORTED, "the 128-point up-channelisation runs on BF_FP32_FFT plans");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (!p->d_tw128) {
+        std::vector<float2> tw(128);
+        for (int u = 0; u < 8; ++u)
+            for (int k = 0; k < 16; ++k) {
+                const double a = kTwoPi * (double)(u * k) / 128.0;
+                tw[u * 16 + k] = make_float2((float)std::cos(a), (float)-std::sin(a));
+            }
+        if ((e = hipMalloc(&p->d_tw128, 128 * sizeof(float2))) != hipSuccess)
+            return fail(p, BF_E_NOMEM, "w128 table");
+        if ((e = hipMemcpy(p->d_tw128, tw.data(), 128 * sizeof(float2), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+            return hip_fail(p, e, "w128 table upload");
+    }
+    // whole frames per chunk (so a channel-frame's tables are its row mod
+    // n_chan), about 256 channel-frames of first-pass output at a time
+    const int32_t n_it = p->cfg.n_time / bf::kUp;
+    const size_t per_unit = (size_t)n_it * bf::kFinePerIter;
+    const int32_t frames_per_chunk = std::max<int32_t>(1, 256 / p->n_chan);
+    const size_t chunk_units = (size_t)frames_per_chunk * p->n_chan;
+    if (p->fine_cap_units < chunk_units) {
+        if (p->d_fine) (void)hipFree(p->d_fine);
+        p->d_fine = nullptr;
+        p->fine_cap_units = 0;
+        if ((e = hipMalloc(&p->d_fine, chunk_units * per_unit * sizeof(float2))) != hipSuccess)
+            return fail(p, BF_E_NOMEM, std::string("up-channelisation workspace: ") +
+                                           hipGetErrorString(e));
+        p->fine_cap_units = chunk_units;
+    }
+    for (int32_t f0 = 0; f0 < n_frames; f0 += frames_per_chunk) {
+        const int32_t nf = std::min(frames_per_chunk, n_frames - f0);
+        const size_t u0 = (size_t)f0 * p->n_chan;
+        bf::LaunchArgs a{};
+        a.in = d_in + u0 * p->cfg.n_time * bf::kInputs;
+        a.lut = p->d_lut;
+        a.ew = p->d_ew;
+        a.tw = p->d_tw;
+        a.mf = p->d_mf;
+        a.n_chan = p->n_chan;
+        a.n_units = nf * p->n_chan;
+        a.n_blk = n_it;
+        a.n_time = p->cfg.n_time;
+        a.sym_ew = p->sym_ew;
+        a.fine = p->d_fine;
+        if ((e = bf::launch_fp32(a, s)) != hipSuccess) return hip_fail(p, e, "first-pass launch");
+        bf::UpchanArgs ua{};
+        ua.fine = p->d_fine;
+        ua.tw128 = p->d_tw128;
+        ua.out = d_out + u0 * bf::kOutPerUnit;
+        ua.n_units = a.n_units;
+        ua.n_chan = p->n_chan;
+        ua.n_blk128 = p->cfg.n_time / 128;
+        if ((e = bf::launch_upchan128(ua, s)) != hipSuccess) return hip_fail(p, e, "second-pass launch");
+    }
+    return BF_OK;
+}
+
 int32_t beamform_frame_tracking(bf_plan* p, const uint8_t* d_in, int32_t n_frames,
                                 const double* sin_phi_ew, float* d_out, void* stream)
 {
@@ -430,6 +520,8 @@ int32_t beamform_destroy(bf_plan* p)
     if (p->d_ew) (void)hipFree(p->d_ew);
     if (p->d_tw) (void)hipFree(p->d_tw);
     if (p->d_mf) (void)hipFree(p->d_mf);
+    if (p->d_fine) (void)hipFree(p->d_fine);
+    if (p->d_tw128) (void)hipFree(p->d_tw128);
     for (bf_plan::EwTrack& t : p->ew_track) {
         if (t.d) (void)hipFree(t.d);
         if (t.h) (void)hipHostFree(t.h);

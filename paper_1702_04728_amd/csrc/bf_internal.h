@@ -63,10 +63,41 @@ struct LaunchArgs {
     int32_t sym_ew;        // 1: x[3-c] = -x[c] and sin(phi[3-j]) = -sin(phi[j]) exactly
     int32_t split_v;       // matrix-core path: 1 = E-W output also as hi + lo (FP32-class)
     int32_t ew_by_unit;    // 1: ew has one row per unit (batch mode)
+    // 8-bit output (batch mode): out_u8[u][1024][16] = clamp(rint(P scale + offset))
+    // with scale/offset rows u % n_chan; out is unused when out_u8 is set
+    uint8_t* out_u8;
+    const float* scale;
+    const float* offset;
+    // 128-point up-channelisation, first pass (batch mode): block iteration it
+    // takes the 16 samples u + 8 tau of 128-sample block it / 8 (u = it % 8), and
+    // instead of integrating power the kept beams of every (u, sub-channel k,
+    // line (p, j)) go to fine[u_nit][it][k][p * 4 + j][m] (complex FP32)
+    float2* fine;
 };
+
+// Complex values per channel-frame in the first pass's output:
+// (n_time / 16 block iterations) x 16 sub-channels x 8 lines x 256 beams.
+constexpr size_t kFinePerIter = 16 * 8 * 256;
 
 hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream);
 hipError_t launch_mfma(const LaunchArgs& a, hipStream_t stream);
+
+// Second pass of the 128-point up-channelisation: fine[unit][24][16][8][256]
+// (first-pass output) -> out[unit][1024][16] Stokes I, or 8-bit codes when
+// out_u8 is set (scale/offset rows unit % n_chan).  tw128[u * 16 + k] =
+// w128^(u k) (FP64 rounded once).
+struct UpchanArgs {
+    const float2* fine;
+    const float2* tw128;
+    float* out;
+    uint8_t* out_u8;
+    const float* scale;
+    const float* offset;
+    int32_t n_units;
+    int32_t n_chan;
+    int32_t n_blk128;   // 128-sample blocks per frame
+};
+hipError_t launch_upchan128(const UpchanArgs& a, hipStream_t stream);
 
 // Matrix-core tables of the FP16 path, in per-lane fragment order:
 //   [8][64] x 8 halves  stage-1 DFT-32 block, tile tau in 0..3, hi then lo

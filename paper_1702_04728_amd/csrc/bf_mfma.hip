@@ -287,7 +287,7 @@ void bf_mfma_kernel(LaunchArgs a)
             for (int i = 0; i < 4; ++i)
                 P[(s2 * 4 + j) * 512 + n + 16 * nu + 32 * (4 * q + i)] = acc[j][nu][i];
     __syncthreads();
-    write_beams(P, a.lut + (size_t)io.row * kBeamNS, io.out, wk.s0, t);
+    write_output(P, a, io, wk.s0, t);
 }
 
 }  // namespace

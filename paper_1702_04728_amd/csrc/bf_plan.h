@@ -30,5 +30,10 @@ struct bf_plan {
         hipEvent_t done = nullptr;
     } ew_track[2];
     int ew_track_next = 0;
+    // 128-point up-channelisation: first-pass workspace (capacity in
+    // channel-frames) and the w128^(u k) table
+    float2* d_fine = nullptr;
+    size_t fine_cap_units = 0;
+    float2* d_tw128 = nullptr;
     std::string err;
 };

@@ -1,0 +1,106 @@
+"""GPU tests of the paper's 128-point up-channelisation (beamform_frame_upchan128;
+Sec. 3 and Sec. 3.2): per-output parity with the oracle (128-point DFTs of
+128-sample blocks, fine bins grouped 8 to a sub-channel), the closed-form
+relations to the 16-point path (a channel-centre tone: same sub-channel, 8 times
+the power; any input: 8 times the total power), several workspace chunks, and
+the unsupported configurations."""
+import numpy as np
+import pytest
+
+import synth
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    torch.cuda.init()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bfm():
+    import paper_1702_04728_amd as bf
+    bf.load_library()
+    return bf
+
+
+def _run(torch_mod, bfm, raw, freqs, upchan, **kw):
+    print("upchan%d run: raw %s %s" % (upchan, raw.shape, kw), flush=True)
+    with bfm.Beamformer(freqs, n_time=raw.shape[2], **kw) as b:
+        out = b.frame(torch_mod.from_numpy(np.ascontiguousarray(raw)).cuda(), upchan=upchan)
+        torch_mod.cuda.synchronize()
+        return out.cpu().numpy().astype(np.float64)
+
+
+def test_config0_parity(torch_mod, bfm, oracle_mod):
+    c = synth.config0()
+    got = _run(torch_mod, bfm, c["raw"], c["freqs"], 128)
+    ref = oracle_mod.beamform_upchan128(oracle_mod.Geometry(), c["freqs"], c["raw"])
+    err = np.abs(got - ref) / ref
+    print("upchan128 config0 max rel err %.3e" % err.max())
+    assert err.max() <= TOL
+    b, q = np.unravel_index(np.argmax(got[0, 0]), got[0, 0].shape)
+    assert (b, q) == (3 * 256 + 171, 8)
+
+
+@pytest.mark.parametrize("n_frames,n_chan,seed", [(3, 2, 41), (1, 5, 42)])
+def test_uniform_bytes_parity(torch_mod, bfm, oracle_mod, n_frames, n_chan, seed):
+    raw = synth.uniform_bytes(seed, (n_frames, n_chan, 384, 2048))
+    freqs = synth.chan_freq_hz(np.random.default_rng(seed).integers(0, 1024, n_chan))
+    got = _run(torch_mod, bfm, raw, freqs, 128)
+    ref = oracle_mod.beamform_upchan128(oracle_mod.Geometry(), freqs, raw)
+    err = np.abs(got - ref) / ref
+    print("upchan128 %dx%d max rel err %.3e" % (n_frames, n_chan, err.max()))
+    assert err.max() <= TOL
+
+
+def test_many_chunks_sampled(torch_mod, bfm, oracle_mod):
+    """300 channels: one frame per workspace chunk, 3 chunks; seeded channel-frames
+    against the oracle."""
+    n_frames, n_chan = 3, 300
+    raw = synth.noise_frames(43, 1, 1)
+    raw = np.ascontiguousarray(np.broadcast_to(raw, (n_frames, n_chan, 384, 2048)))
+    rng = np.random.default_rng(43)
+    freqs = synth.chan_freq_hz(rng.permutation(1024)[:n_chan])
+    got = _run(torch_mod, bfm, raw, freqs, 128)
+    units = [(int(f), int(c)) for f, c in zip(rng.integers(0, n_frames, 6), rng.integers(0, n_chan, 6))]
+    ref = oracle_mod.beamform_upchan128(oracle_mod.Geometry(), freqs, raw, units=units)
+    for i, (f, c) in enumerate(units):
+        err = np.abs(got[f, c] - ref[i]) / ref[i]
+        assert err.max() <= TOL, (f, c, err.max())
+
+
+def test_closed_form_relations_to_16_point(torch_mod, bfm):
+    """Channel-centre tone (exact integer samples): sub-channel 8 only, 8 times the
+    16-point power (3 x 128^2 against 24 x 16^2); uniform bytes: total power 8 times
+    the 16-point total (Parseval)."""
+    tone = np.empty((1, 1, 384, 2048), np.uint8)
+    synth.channel_frames(None, 600e6, 1, [synth.Source(0.3, 0.2, 3.0)], tone[:, 0], sigma=0.0)
+    a16 = _run(torch_mod, bfm, tone, [600e6], 16)[0, 0]
+    a128 = _run(torch_mod, bfm, tone, [600e6], 128)[0, 0]
+    assert np.allclose(a128[:, 8], 8 * a16[:, 8], rtol=TOL, atol=0)
+    assert np.abs(np.delete(a128, 8, axis=1)).max() <= 1e-6 * a128.max()
+    rnd = synth.uniform_bytes(44, (2, 3, 384, 2048))
+    f = synth.chan_freq_hz([10, 500, 1000])
+    t16 = _run(torch_mod, bfm, rnd, f, 16).sum(axis=-1)
+    t128 = _run(torch_mod, bfm, rnd, f, 128).sum(axis=-1)
+    assert np.allclose(t128, 8 * t16, rtol=TOL, atol=0)
+
+
+def test_unsupported_configurations(torch_mod, bfm):
+    raw = torch_mod.zeros((1, 1, 384, 2048), dtype=torch_mod.uint8, device="cuda")
+    with bfm.Beamformer([600e6], precision="fp16") as b:
+        with pytest.raises(bfm.BeamformError):
+            b.frame(raw, upchan=128)
+    short = torch_mod.zeros((1, 1, 48, 2048), dtype=torch_mod.uint8, device="cuda")
+    with bfm.Beamformer([600e6], n_time=48) as b:
+        with pytest.raises(bfm.BeamformError):
+            b.frame(short, upchan=128)
+        with pytest.raises(ValueError):
+            b.frame(short, upchan=64)

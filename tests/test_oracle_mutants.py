@@ -5,9 +5,9 @@ directory), builds it, routes the oracle binding through it and runs the pin
 suite: at least one pin must fail.  The real oracle is untouched.
 """
 import inspect
+import multiprocessing
 import os
 
-import pytest
 
 import oracle
 import test_oracle_pins as pins
@@ -77,14 +77,32 @@ def _run_pins(oracle_mod):
     return failed
 
 
-@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_pins_catch_planted_mistake(tmp_path, name, old, new):
-    assert SRC.count(old) == 1, "mutation anchor not unique: %s" % name
-    lib = oracle.build_variant(SRC.replace(old, new), str(tmp_path / "liboracle_mutant.so"))
+def _mutant_worker(job):
+    """Build one mutant in its own directory and run every pin against it."""
+    name, old, new, workdir = job
+    lib = oracle.build_variant(SRC.replace(old, new), os.path.join(workdir, "liboracle_mutant.so"))
     with oracle.use_library(lib):
-        failed = _run_pins(oracle)
-    print("%s: caught by %s" % (name, failed))
-    assert failed, "no pin detects: %s" % name
+        return name, _run_pins(oracle)
+
+
+def test_pins_catch_planted_mistakes(tmp_path):
+    for name, old, _ in MUTANTS:
+        assert SRC.count(old) == 1, "mutation anchor not unique: %s" % name
+    jobs = []
+    for i, (name, old, new) in enumerate(MUTANTS):
+        d = tmp_path / ("m%02d" % i)
+        d.mkdir()
+        jobs.append((name, old, new, str(d)))
+    workers = max(1, min(8, (os.cpu_count() or 2) // 2))
+    ctx = multiprocessing.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        results = pool.map(_mutant_worker, jobs)
+    missed = []
+    for name, failed in results:
+        print("%s: caught by %s" % (name, failed))
+        if not failed:
+            missed.append(name)
+    assert not missed, "no pin detects: %s" % missed
 
 
 def test_unmodified_oracle_passes_all_pins():
