@@ -132,9 +132,11 @@ int32_t beamform_frame(bf_plan *plan, const uint8_t *d_in, int32_t n_frames, flo
  * phase, sub-channel) to a plan-owned workspace (6.3 MB per channel-frame,
  * allocated at the first call, about 256 channel-frames or one frame at a
  * time), the second kernel completes the 128-point transforms and integrates.
+ * The plan's precision applies to the first pass (the spatial transforms);
+ * the second pass is FP32.
  *   d_in, d_out: as beamform_frame (d_out fully overwritten).
- * Needs n_time % 128 == 0 and a BF_FP32_FFT plan (else BF_E_UNSUPPORTED);
- * BF_E_NOMEM if the workspace cannot be allocated. */
+ * Needs n_time % 128 == 0 (else BF_E_UNSUPPORTED); BF_E_NOMEM if the workspace
+ * cannot be allocated. */
 int32_t beamform_frame_upchan128(bf_plan *plan, const uint8_t *d_in, int32_t n_frames,
                                  float *d_out, void *stream);
 

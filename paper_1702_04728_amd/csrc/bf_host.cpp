@@ -381,8 +381,6 @@ int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_fram
     if (st != BF_OK || n_frames == 0) return st;
     if (p->cfg.n_time % 128 != 0)
         return fail(p, BF_E_UNSUPPORTED, "the 128-point up-channelisation needs n_time % 128 == 0");
-    if (p->cfg.precision != BF_FP32_FFT)
-        return fail(p, BF_E_UNSUPPORTED, "the 128-point up-channelisation runs on BF_FP32_FFT plans");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     if (!p->d_tw128) {
@@ -427,8 +425,10 @@ int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_fram
         a.n_blk = n_it;
         a.n_time = p->cfg.n_time;
         a.sym_ew = p->sym_ew;
+        a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
         a.fine = p->d_fine;
-        if ((e = bf::launch_fp32(a, s)) != hipSuccess) return hip_fail(p, e, "first-pass launch");
+        e = p->cfg.precision == BF_FP32_FFT ? bf::launch_fp32(a, s) : bf::launch_mfma(a, s);
+        if (e != hipSuccess) return hip_fail(p, e, "first-pass launch");
         bf::UpchanArgs ua{};
         ua.fine = p->d_fine;
         ua.tw128 = p->d_tw128;

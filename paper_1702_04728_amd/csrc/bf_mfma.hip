@@ -127,11 +127,14 @@ __device__ __forceinline__ void ew_phase(const float2 (&y)[4], const float2 (&W)
 // kSplitV: also carry the E-W output as hi + lo (stage 1 sums hi*hi + lo*hi +
 // hi*lo): every operand then holds ~22 significant bits and the result is
 // FP32-class (max relative power error ~1e-6 against FP64).
-template <bool kSym, bool kSplitV>
+// kFine: first pass of the 128-point up-channelisation (stride-8 sample
+// blocks; each line's kept beams written out instead of its power summed).
+template <bool kSym, bool kSplitV, bool kFine>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bf_mfma_kernel(LaunchArgs a)
 {
     __shared__ __align__(16) float4 s_T[4 * 1024];  // time-DFT output, then per-bin powers
+    __shared__ __align__(16) float2 s_bins[kFine ? 4 * 512 : 1];  // per wave: one line's bins
 
     const Work wk = work_of_block();
     UnitIO io;
@@ -165,7 +168,7 @@ void bf_mfma_kernel(LaunchArgs a)
 
     const uint8_t* src = io.in;
     uint2 raw[16];
-    load_block(src, raw, t);
+    load_block(block_base<kFine>(src, 0), raw, t, block_stride<kFine>());
 
     float acc[4][2][4];  // [E-W beam j][c = n + 16 nu][d = 4 q + i]
     constexpr int kAcc = sizeof(acc) / sizeof(float);
@@ -183,7 +186,7 @@ void bf_mfma_kernel(LaunchArgs a)
     for (int blk = 0; blk < a.n_blk; ++blk) {
         time_dft_class(wk.s0, raw, s_T, t);
         __syncthreads();
-        if (blk + 1 < a.n_blk) load_block(src + (size_t)(blk + 1) * (kUp * kInputs), raw, t);
+        if (blk + 1 < a.n_blk) load_block(block_base<kFine>(src, blk + 1), raw, t, block_stride<kFine>());
 
         // E-W phasing straight into stage-1 A fragments: feeds 16 a + n, a = 4q + ia
         half8 A[4][2];
@@ -266,12 +269,26 @@ void bf_mfma_kernel(LaunchArgs a)
                         X[mu] = mfma16(FDl[mu], Bh[nu], X[mu]);
                         X[mu] = mfma16(FDh[mu], Bl[nu], X[mu]);
                     }
+                    if constexpr (kFine) {  // bin n + 16 nu + 32 (4 q + i): (re, im) = (X[0], X[1])
+                        float2* bins = s_bins + s2 * 512;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        acc[j][nu][i] = fmaf(X[0][i], X[0][i], fmaf(X[1][i], X[1][i], acc[j][nu][i]));
+                        for (int i = 0; i < 4; ++i)
+                            bins[n + 16 * nu + 32 * (4 * q + i)] = make_float2(X[0][i], X[1][i]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            acc[j][nu][i] = fmaf(X[0][i], X[0][i], fmaf(X[1][i], X[1][i], acc[j][nu][i]));
+                    }
+                }
+                if constexpr (kFine) {
+                    wave_lds_sync();
+                    write_fine_line(s_bins + s2 * 512, a.lut + (size_t)io.row * kBeamNS,
+                                    fine_line_ptr(a, wk.unit, blk, wk.s0 + 4 * s2, p * 4 + j), lane, 64);
+                    wave_lds_sync();
                 }
             }
     }
+    if constexpr (kFine) return;  // the second pass detects and integrates
 
     if (!io.last) {  // frame continues in the next chunk's launch
         store_partial<kAcc>(&acc[0][0][0], io.partial, t);
@@ -298,12 +315,20 @@ hipError_t launch_mfma(const LaunchArgs& a, hipStream_t stream)
     LaunchArgs args = a;
     void* params[] = {&args};
     const void* k;
-    if (a.split_v)
-        k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true, true>)
-                     : reinterpret_cast<const void*>(&bf_mfma_kernel<false, true>);
-    else
-        k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true, false>)
-                     : reinterpret_cast<const void*>(&bf_mfma_kernel<false, false>);
+    if (a.fine) {
+        if (a.split_v)
+            k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true, true, true>)
+                         : reinterpret_cast<const void*>(&bf_mfma_kernel<false, true, true>);
+        else
+            k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true, false, true>)
+                         : reinterpret_cast<const void*>(&bf_mfma_kernel<false, false, true>);
+    } else if (a.split_v) {
+        k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true, true, false>)
+                     : reinterpret_cast<const void*>(&bf_mfma_kernel<false, true, false>);
+    } else {
+        k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true, false, false>)
+                     : reinterpret_cast<const void*>(&bf_mfma_kernel<false, false, false>);
+    }
     return hipLaunchKernel(k, dev::grid_for(a.n_units), dim3(dev::kThreads), params, 0, stream);
 }
 

@@ -1,5 +1,5 @@
 """GPU tests of the paper's 128-point up-channelisation (beamform_frame_upchan128;
-Sec. 3 and Sec. 3.2): per-output parity with the oracle (128-point DFTs of
+Sec. 3 and Sec. 3.2), all three precisions: per-output parity with the oracle (128-point DFTs of
 128-sample blocks, fine bins grouped 8 to a sub-channel), the closed-form
 relations to the 16-point path (a channel-centre tone: same sub-channel, 8 times
 the power; any input: 8 times the total power), several workspace chunks, and
@@ -38,26 +38,43 @@ def _run(torch_mod, bfm, raw, freqs, upchan, **kw):
         return out.cpu().numpy().astype(np.float64)
 
 
-def test_config0_parity(torch_mod, bfm, oracle_mod):
+TOLS = {"fp32": 1e-5, "fp16": 2e-3, "fp32_mfma": 1e-5}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp32_mfma"])
+def test_config0_parity(torch_mod, bfm, oracle_mod, precision):
     c = synth.config0()
-    got = _run(torch_mod, bfm, c["raw"], c["freqs"], 128)
+    got = _run(torch_mod, bfm, c["raw"], c["freqs"], 128, precision=precision)
     ref = oracle_mod.beamform_upchan128(oracle_mod.Geometry(), c["freqs"], c["raw"])
     err = np.abs(got - ref) / ref
-    print("upchan128 config0 max rel err %.3e" % err.max())
-    assert err.max() <= TOL
+    print("upchan128 config0 %s max rel err %.3e" % (precision, err.max()))
+    assert err.max() <= TOLS[precision]
     b, q = np.unravel_index(np.argmax(got[0, 0]), got[0, 0].shape)
     assert (b, q) == (3 * 256 + 171, 8)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp32_mfma"])
 @pytest.mark.parametrize("n_frames,n_chan,seed", [(3, 2, 41), (1, 5, 42)])
-def test_uniform_bytes_parity(torch_mod, bfm, oracle_mod, n_frames, n_chan, seed):
+def test_uniform_bytes_parity(torch_mod, bfm, oracle_mod, n_frames, n_chan, seed, precision):
     raw = synth.uniform_bytes(seed, (n_frames, n_chan, 384, 2048))
     freqs = synth.chan_freq_hz(np.random.default_rng(seed).integers(0, 1024, n_chan))
-    got = _run(torch_mod, bfm, raw, freqs, 128)
+    got = _run(torch_mod, bfm, raw, freqs, 128, precision=precision)
     ref = oracle_mod.beamform_upchan128(oracle_mod.Geometry(), freqs, raw)
     err = np.abs(got - ref) / ref
-    print("upchan128 %dx%d max rel err %.3e" % (n_frames, n_chan, err.max()))
-    assert err.max() <= TOL
+    print("upchan128 %dx%d %s max rel err %.3e" % (n_frames, n_chan, precision, err.max()))
+    assert err.max() <= TOLS[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp16", "fp32_mfma"])
+def test_general_geometry_parity(torch_mod, bfm, oracle_mod, precision):
+    """E-W directions without mirror symmetry take the matrix-core kernels' general form."""
+    raw = synth.uniform_bytes(45, (1, 2, 384, 2048))
+    freqs = synth.chan_freq_hz([300, 800])
+    sphi = np.sin(np.deg2rad([-0.5, -0.1, 0.25, 0.7]))
+    got = _run(torch_mod, bfm, raw, freqs, 128, precision=precision, sin_phi_ew=sphi)
+    ref = oracle_mod.beamform_upchan128(oracle_mod.Geometry(sin_phi_ew=sphi), freqs, raw)
+    err = np.abs(got - ref) / ref
+    assert err.max() <= TOLS[precision]
 
 
 def test_many_chunks_sampled(torch_mod, bfm, oracle_mod):
@@ -94,10 +111,6 @@ def test_closed_form_relations_to_16_point(torch_mod, bfm):
 
 
 def test_unsupported_configurations(torch_mod, bfm):
-    raw = torch_mod.zeros((1, 1, 384, 2048), dtype=torch_mod.uint8, device="cuda")
-    with bfm.Beamformer([600e6], precision="fp16") as b:
-        with pytest.raises(bfm.BeamformError):
-            b.frame(raw, upchan=128)
     short = torch_mod.zeros((1, 1, 48, 2048), dtype=torch_mod.uint8, device="cuda")
     with bfm.Beamformer([600e6], n_time=48) as b:
         with pytest.raises(bfm.BeamformError):
