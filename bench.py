@@ -46,6 +46,9 @@ PEAK = {"fp32": (157.3, "TFLOP/s", "alu"),    # MI355X FP32 vector peak (publish
 HBM_PEAK_GBS = 8000.0
 KERNEL_NAME = {"fp32": "bf_fp32_kernel<false>", "fp16": "bf_mfma_kernel<true, false, false>",
                "fp32_mfma": "bf_mfma_kernel<true, true, false>"}
+# first pass of the 128-point up-channelisation
+FINE_KERNEL_NAME = {"fp32": "bf_fp32_kernel<true>", "fp16": "bf_mfma_kernel<true, false, true>",
+                    "fp32_mfma": "bf_mfma_kernel<true, true, true>"}
 # directions without mirror symmetry (tracking beams) take the general E-W form
 KERNEL_NAME_GENERAL = {"fp32": "bf_fp32_kernel<false>", "fp16": "bf_mfma_kernel<false, false, false>",
                        "fp32_mfma": "bf_mfma_kernel<false, true, false>"}
@@ -161,6 +164,13 @@ def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None, u8=None, u
     flops = FLOPS_PER_UNIT[prec] * units
     peak, punit, bound = PEAK[prec]
     achieved = flops / kern_s / 1e12
+    kernel = (KERNEL_NAME if sin_phi is None else KERNEL_NAME_GENERAL)[prec]
+    if upchan == 128:
+        # two passes moving the beams through HBM: bound by memory, quoted as
+        # algorithmic bytes per call over the call's duration (both passes)
+        peak, punit, bound = HBM_PEAK_GBS, "GB/s", "hbm"
+        achieved = unit_bytes * units / kern_s / 1e9
+        kernel = FINE_KERNEL_NAME[prec] + " + bf_upchan128_kernel"
     return {
         "value": round(units / (ms_step * 1e-3) * FRAME_S, 2),
         "ms_per_step": round(ms_step, 5),
@@ -169,8 +179,7 @@ def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None, u8=None, u
                      "unit": punit, "frac": round(achieved / peak, 4),
                      "traffic": (traffic_from_profiles(prec, units)
                                  if sin_phi is None and not u8 and upchan == 16 else None),
-                     "kernel": (KERNEL_NAME if sin_phi is None else KERNEL_NAME_GENERAL)[prec],
-                     "flops_per_launch": flops},
+                     "kernel": kernel, "flops_per_launch": flops},
         "hbm": {"achieved_GBs": round(unit_bytes * units / kern_s / 1e9, 1),
                 "peak_GBs": HBM_PEAK_GBS,
                 "frac": round(unit_bytes * units / kern_s / 1e9 / HBM_PEAK_GBS, 4),
