@@ -140,6 +140,20 @@ int32_t beamform_frame(bf_plan *plan, const uint8_t *d_in, int32_t n_frames, flo
 int32_t beamform_frame_upchan128(bf_plan *plan, const uint8_t *d_in, int32_t n_frames,
                                  float *d_out, void *stream);
 
+/* Test aid: the complex beams before detection (Sec. 3: the beamforming
+ * kernel's output, here already up-channelised) for one frame of every
+ * channel: for channel c, 16-sample block b, time-DFT bin s (not centre-
+ * shifted), pol p, E-W beam j and N-S beam m,
+ *   U = sum_{tau < 16} B[16 b + tau] exp(-2 pi i s tau / 16),
+ * B the beam (j, m) of pol p (N-S bin from Eq. (1), E-W exact phasing), in
+ * the plan's precision.
+ *   d_in:     device u8 [n_chan][n_time][2048] (one frame), 16-byte aligned;
+ *   d_ns_out: device f32 [n_chan][n_time / 16][16][2][4][256][2] (re, im),
+ *             16-byte aligned, fully overwritten (6.3 MB per channel).
+ * Squaring, summing the pols and the blocks and centre-shifting s gives
+ * beamform_frame's output. */
+int32_t beamform_debug_ns(bf_plan *plan, const uint8_t *d_in, float *d_ns_out, void *stream);
+
 /* 8-bit output (Sec. 3 and Table 1: the integrated Stokes I beams leave the
  * beamformer rescaled to 8-bit integers; the rule is not given, this is an
  * affine rescale per channel, beam and sub-channel).  As beamform_frame, but

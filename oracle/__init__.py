@@ -184,6 +184,8 @@ def _bind(lib):
     lib.orc_rescale_u8.restype = None
     lib.orc_group_bins.argtypes = [vp, i64, i32, i32, vp]
     lib.orc_group_bins.restype = None
+    lib.orc_beams_unit.argtypes = [gp, f64, vp, vp, vp]
+    lib.orc_beams_unit.restype = ctypes.c_int
     return lib
 
 
@@ -283,6 +285,21 @@ def upchan(b) -> np.ndarray:
     u = np.empty(b.size, dtype=np.complex128)
     _load().orc_upchan(b.size, _ptr(b), _ptr(u))
     return u
+
+
+def beams_unit(geom: Geometry, f_hz: float, raw_unit, lut_override=None) -> np.ndarray:
+    """Complex beams before detection for one channel-frame: complex128
+    [n_time/n_dft][n_dft (bin s, not centre-shifted)][n_pol][n_beam_ew][n_beam_ns]."""
+    raw_unit = np.ascontiguousarray(raw_unit, dtype=np.uint8)
+    assert raw_unit.size == geom.n_time * geom.n_inputs
+    lo = None if lut_override is None else np.ascontiguousarray(lut_override, dtype=np.int32)
+    out = np.empty((geom.n_time // geom.n_dft, geom.n_dft, geom.n_pol, geom.n_beam_ew,
+                    geom.n_beam_ns), dtype=np.complex128)
+    g = geom._c()
+    r = _load().orc_beams_unit(ctypes.byref(g), float(f_hz), _ptr(lo), _ptr(raw_unit), _ptr(out))
+    if r != 0:
+        raise RuntimeError("orc_beams_unit failed (%d)" % r)
+    return out
 
 
 def beamform_unit(geom: Geometry, f_hz: float, raw_unit, lut_override=None) -> np.ndarray:

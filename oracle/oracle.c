@@ -211,22 +211,22 @@ static int orc_check(const orc_geom *g)
 }
 
 /*
- * One channel-frame: raw bytes [n_time][n_cyl*n_feed*n_pol] in, Stokes-I
- * powers [n_beam_ew*n_beam_ns][n_dft] out.  `lut` gives the kept bin per N-S
+ * Steps 1-3 for one channel-frame: decode, N-S zero-padded beams at the kept
+ * bins, E-W exact phasing.  Returns B[p][j][m][t] (complex, time innermost: the
+ * paper's transposed order), allocated here and freed by the caller, or NULL
+ * on bad arguments or allocation failure.  `lut` gives the kept bin per N-S
  * beam; NULL means Eq. (1) at f_hz.
  */
-int orc_beamform_unit(const orc_geom *g, double f_hz, const int32_t *lut,
-                      const uint8_t *in, double *out)
+static double *orc_beams_time(const orc_geom *g, double f_hz, const int32_t *lut,
+                              const uint8_t *in)
 {
-    if (orc_check(g)) return -1;
+    if (orc_check(g)) return NULL;
     const int32_t NF = g->n_feed, NB = g->n_feed * g->pad, NC = g->n_cyl,
-                  NP = g->n_pol, NM = g->n_beam_ns, NJ = g->n_beam_ew,
-                  L = g->n_dft, T = g->n_time;
+                  NP = g->n_pol, NM = g->n_beam_ns, NJ = g->n_beam_ew, T = g->n_time;
     const int64_t n_in = (int64_t)NC * NF * NP;
 
     int32_t *k = (int32_t *)malloc(sizeof(int32_t) * NM);
     double *roots = (double *)malloc(sizeof(double) * 2 * NB);
-    double *roots_l = (double *)malloc(sizeof(double) * 2 * L);
     double *w = (double *)malloc(sizeof(double) * 2 * NJ * NC);
     double *x = (double *)malloc(sizeof(double) * 2 * (size_t)T * n_in);        /* [t][i] */
     double *line = (double *)malloc(sizeof(double) * 2 * NF);
@@ -236,23 +236,18 @@ int orc_beamform_unit(const orc_geom *g, double f_hz, const int32_t *lut,
     /* B[p][j][m][t]: after E-W phasing, time innermost (the paper's transpose) */
     double *B = (double *)malloc(sizeof(double) * 2 * (size_t)NP * NJ * NM * T);
     double *bj = (double *)malloc(sizeof(double) * 2 * NJ);
-    double *u = (double *)malloc(sizeof(double) * 2 * L);
-    if (!k || !roots || !roots_l || !w || !x || !line || !yb || !Y || !B || !bj || !u) {
-        free(k); free(roots); free(roots_l); free(w); free(x); free(line);
-        free(yb); free(Y); free(B); free(bj); free(u);
-        return -2;
+    int ok = k && roots && w && x && line && yb && Y && B && bj;
+    if (ok) {
+        if (lut) memcpy(k, lut, sizeof(int32_t) * NM);
+        else orc_lut(g, f_hz, k);
+        for (int32_t m = 0; m < NM; ++m)
+            if (k[m] < 0 || k[m] >= NB) ok = 0;
     }
-
-    if (lut) memcpy(k, lut, sizeof(int32_t) * NM);
-    else orc_lut(g, f_hz, k);
-    for (int32_t m = 0; m < NM; ++m)
-        if (k[m] < 0 || k[m] >= NB) {
-            free(k); free(roots); free(roots_l); free(w); free(x); free(line);
-            free(yb); free(Y); free(B); free(bj); free(u);
-            return -1;
-        }
+    if (!ok) {
+        free(k); free(roots); free(w); free(x); free(line); free(yb); free(Y); free(B); free(bj);
+        return NULL;
+    }
     orc_roots(NB, roots);
-    orc_roots(L, roots_l);
     orc_ew_weights(g, f_hz, w);
 
     /* 1. decode */
@@ -288,6 +283,27 @@ int orc_beamform_unit(const orc_geom *g, double f_hz, const int32_t *lut,
                 }
             }
 
+    free(k); free(roots); free(w); free(x); free(line); free(yb); free(Y); free(bj);
+    return B;
+}
+
+/*
+ * One channel-frame: raw bytes [n_time][n_cyl*n_feed*n_pol] in, Stokes-I
+ * powers [n_beam_ew*n_beam_ns][n_dft] out.  `lut` gives the kept bin per N-S
+ * beam; NULL means Eq. (1) at f_hz.
+ */
+int orc_beamform_unit(const orc_geom *g, double f_hz, const int32_t *lut,
+                      const uint8_t *in, double *out)
+{
+    double *B = orc_beams_time(g, f_hz, lut, in);
+    if (!B) return orc_check(g) ? -1 : -2;
+    const int32_t NP = g->n_pol, NM = g->n_beam_ns, NJ = g->n_beam_ew, L = g->n_dft,
+                  T = g->n_time;
+    double *roots_l = (double *)malloc(sizeof(double) * 2 * L);
+    double *u = (double *)malloc(sizeof(double) * 2 * L);
+    if (!roots_l || !u) { free(B); free(roots_l); free(u); return -2; }
+    orc_roots(L, roots_l);
+
     /* 4-5. up-channelise each block of L samples, Stokes I, integrate */
     memset(out, 0, sizeof(double) * (size_t)NJ * NM * L);
     for (int32_t j = 0; j < NJ; ++j)
@@ -303,8 +319,39 @@ int orc_beamform_unit(const orc_geom *g, double f_hz, const int32_t *lut,
                     }
                 }
 
-    free(k); free(roots); free(roots_l); free(w); free(x); free(line);
-    free(yb); free(Y); free(B); free(bj); free(u);
+    free(B); free(roots_l); free(u);
+    return 0;
+}
+
+/*
+ * The complex beams before detection for one channel-frame: the beams of
+ * steps 1-3, each up-channelised per block of L samples (step 4), written as
+ * out[blk][s][p][j][m] (complex; s the DFT bin, not centre-shifted).
+ */
+int orc_beams_unit(const orc_geom *g, double f_hz, const int32_t *lut, const uint8_t *in,
+                   double *out)
+{
+    double *B = orc_beams_time(g, f_hz, lut, in);
+    if (!B) return orc_check(g) ? -1 : -2;
+    const int32_t NP = g->n_pol, NM = g->n_beam_ns, NJ = g->n_beam_ew, L = g->n_dft,
+                  T = g->n_time;
+    double *roots_l = (double *)malloc(sizeof(double) * 2 * L);
+    double *u = (double *)malloc(sizeof(double) * 2 * L);
+    if (!roots_l || !u) { free(B); free(roots_l); free(u); return -2; }
+    orc_roots(L, roots_l);
+    for (int32_t p = 0; p < NP; ++p)
+        for (int32_t j = 0; j < NJ; ++j)
+            for (int32_t m = 0; m < NM; ++m)
+                for (int32_t blk = 0; blk < T / L; ++blk) {
+                    size_t ob = (((size_t)p * NJ + j) * NM + m) * T + (size_t)blk * L;
+                    orc_upchan_tab(L, roots_l, &B[2 * ob], u);
+                    for (int32_t s = 0; s < L; ++s) {
+                        size_t o = ((((size_t)blk * L + s) * NP + p) * NJ + j) * NM + m;
+                        out[2 * o] = u[2 * s];
+                        out[2 * o + 1] = u[2 * s + 1];
+                    }
+                }
+    free(B); free(roots_l); free(u);
     return 0;
 }
 

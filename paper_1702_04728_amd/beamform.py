@@ -30,6 +30,7 @@ N_BEAM_NS = 256
 EXPORTED = (
     "beamform_default_config", "beamform_compute_lut", "beamform_init", "beamform_frame",
     "beamform_frame_upchan128", "beamform_frame_u8", "beamform_frame_tracking",
+    "beamform_debug_ns",
     "beamform_stream", "beamform_stream_schedule", "beamform_get_lut", "beamform_plan_info",
     "beamform_destroy", "beamform_strerror", "beamform_last_error",
 )
@@ -151,6 +152,7 @@ def load_library():
         "beamform_frame_tracking": ([vp, vp, i32, vp, vp, vp], i32),
         "beamform_frame_u8": ([vp, vp, i32, vp, vp, vp, vp], i32),
         "beamform_frame_upchan128": ([vp, vp, i32, vp, vp], i32),
+        "beamform_debug_ns": ([vp, vp, vp, vp], i32),
         "beamform_stream": ([vp, ctypes.POINTER(BfStreamDesc), ctypes.POINTER(BfStreamStats), vp],
                             i32),
         "beamform_stream_schedule": ([ctypes.POINTER(BfStreamDesc), ctypes.c_int64,
@@ -314,6 +316,24 @@ class Beamformer:
                 _stream_handle(stream))
         _check(st, self._plan)
         return out
+
+    def debug_ns(self, raw, stream=None):
+        """Test aid: complex beams before detection for one frame, raw CUDA uint8
+        [n_chan][n_time][2048] -> CUDA complex64 [n_chan][n_time/16][16 (bin s,
+        not centre-shifted)][2 pols][4 E-W][256 N-S]."""
+        import torch
+        if self._plan is None:
+            raise BeamformError(-4, "plan destroyed")
+        if not (isinstance(raw, torch.Tensor) and raw.is_cuda and raw.dtype == torch.uint8
+                and raw.is_contiguous() and tuple(raw.shape) == (self.n_chan, self.n_time, N_INPUTS)):
+            raise ValueError("raw must be a contiguous CUDA uint8 [%d][%d][%d]"
+                             % (self.n_chan, self.n_time, N_INPUTS))
+        out = torch.empty((self.n_chan, self.n_time // 16, 16, 2, 4, N_BEAM_NS, 2),
+                          dtype=torch.float32, device=raw.device)
+        st = self.lib.beamform_debug_ns(self._plan, ctypes.c_void_p(raw.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+        _check(st, self._plan)
+        return torch.view_as_complex(out)
 
     def frame_u8(self, raw, scale, offset, out=None, stream=None):
         """8-bit output: code = clamp(rint(P * scale + offset), 0, 255) per output,

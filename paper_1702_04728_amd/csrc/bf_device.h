@@ -254,24 +254,23 @@ __device__ __forceinline__ void load_block(const uint8_t* __restrict__ blk, uint
         raw[tau] = *reinterpret_cast<const uint2*>(blk + tau * stride + 8 * t);
 }
 
-// Samples of block iteration `it`: 16 consecutive samples, or (kFine, the
+// Samples of block iteration `it`: 16 consecutive samples, or (stride8, the
 // first pass of the 128-point up-channelisation) the samples u + 8 tau of
 // 128-sample block it / 8 with u = it % 8, so that the 16-point time DFT is
 // the first step of a 128-point DFT split as 128 = 16 (tau) x 8 (u).
-template <bool kFine>
-__device__ __forceinline__ const uint8_t* block_base(const uint8_t* in, int it)
+__device__ __forceinline__ const uint8_t* block_base(const uint8_t* in, int it, bool stride8)
 {
-    if constexpr (kFine) return in + (size_t)((it >> 3) * 128 + (it & 7)) * kInputs;
-    else return in + (size_t)it * (kUp * kInputs);
+    return stride8 ? in + (size_t)((it >> 3) * 128 + (it & 7)) * kInputs
+                   : in + (size_t)it * (kUp * kInputs);
 }
-template <bool kFine>
-__device__ __forceinline__ int block_stride()
+__device__ __forceinline__ int block_stride(bool stride8)
 {
-    return kFine ? 8 * kInputs : kInputs;
+    return stride8 ? 8 * kInputs : kInputs;
 }
 
-// First pass of the 128-point up-channelisation: the 512 bins of one line
-// (sub-channel k, line p * 4 + j, block iteration it) sit in LDS at bins[];
+// Complex beams out (first pass of the 128-point up-channelisation, or the
+// pre-detection beams): the 512 bins of one line (sub-channel k, line
+// p * 4 + j, block iteration it) sit in LDS at bins[];
 // the kept beam of every N-S pointing m is bins[lut[m]].  Lanes `lane` of
 // `n_lanes` write consecutive m.
 __device__ __forceinline__ void write_fine_line(const float2* __restrict__ bins,

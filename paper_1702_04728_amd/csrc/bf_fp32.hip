@@ -171,7 +171,8 @@ void bf_fp32_kernel(LaunchArgs a)
     float2* bufO = bufE + kXpBuf;
 
     uint2 raw[16];
-    load_block(block_base<kFine>(src, 0), raw, t, block_stride<kFine>());
+    const bool s8 = kFine && a.fine_stride8;
+    load_block(block_base(src, 0, s8), raw, t, block_stride(s8));
 
     float acc[2][16];
     constexpr int kAcc = sizeof(acc) / sizeof(float);
@@ -187,7 +188,7 @@ void bf_fp32_kernel(LaunchArgs a)
         time_dft_class(wk.s0, raw, T, t);
         __syncthreads();
         // prefetch the next block's samples while the transforms run
-        if (blk + 1 < a.n_blk) load_block(block_base<kFine>(src, blk + 1), raw, t, block_stride<kFine>());
+        if (blk + 1 < a.n_blk) load_block(block_base(src, blk + 1, s8), raw, t, block_stride(s8));
         // B1: E-W phasing while loading this group's two lines (feeds 16 a + b)
         float2 v0[16], v1[16];
 #pragma unroll

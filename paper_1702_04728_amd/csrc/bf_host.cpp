@@ -427,6 +427,7 @@ int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_fram
         a.sym_ew = p->sym_ew;
         a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
         a.fine = p->d_fine;
+        a.fine_stride8 = 1;
         e = p->cfg.precision == BF_FP32_FFT ? bf::launch_fp32(a, s) : bf::launch_mfma(a, s);
         if (e != hipSuccess) return hip_fail(p, e, "first-pass launch");
         bf::UpchanArgs ua{};
@@ -438,6 +439,32 @@ int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_fram
         ua.n_blk128 = p->cfg.n_time / 128;
         if ((e = bf::launch_upchan128(ua, s)) != hipSuccess) return hip_fail(p, e, "second-pass launch");
     }
+    return BF_OK;
+}
+
+int32_t beamform_debug_ns(bf_plan* p, const uint8_t* d_in, float* d_ns_out, void* stream)
+{
+    if (!p) return BF_E_INVAL;
+    p->err.clear();
+    int32_t st = check_batch(p, d_in, 1, d_ns_out);
+    if (st != BF_OK) return st;
+    bf::LaunchArgs a{};
+    a.in = d_in;
+    a.lut = p->d_lut;
+    a.ew = p->d_ew;
+    a.tw = p->d_tw;
+    a.mf = p->d_mf;
+    a.n_chan = p->n_chan;
+    a.n_units = p->n_chan;
+    a.n_blk = p->cfg.n_time / bf::kUp;
+    a.n_time = p->cfg.n_time;
+    a.sym_ew = p->sym_ew;
+    a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
+    a.fine = reinterpret_cast<float2*>(d_ns_out);
+    a.fine_stride8 = 0;
+    hipError_t e = p->cfg.precision == BF_FP32_FFT ? bf::launch_fp32(a, (hipStream_t)stream)
+                                                   : bf::launch_mfma(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
     return BF_OK;
 }
 

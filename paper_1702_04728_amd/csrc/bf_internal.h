@@ -68,11 +68,14 @@ struct LaunchArgs {
     uint8_t* out_u8;
     const float* scale;
     const float* offset;
-    // 128-point up-channelisation, first pass (batch mode): block iteration it
-    // takes the 16 samples u + 8 tau of 128-sample block it / 8 (u = it % 8), and
-    // instead of integrating power the kept beams of every (u, sub-channel k,
-    // line (p, j)) go to fine[u_nit][it][k][p * 4 + j][m] (complex FP32)
+    // Complex beams out (batch mode): instead of integrating power, the kept
+    // beams of every (block iteration it, sub-channel k, line (p, j)) go to
+    // fine[unit][it][k][p * 4 + j][m] (complex FP32).  With fine_stride8 (the
+    // first pass of the 128-point up-channelisation) iteration it takes the 16
+    // samples u + 8 tau of 128-sample block it / 8 (u = it % 8), else 16
+    // consecutive samples (the pre-detection beams).
     float2* fine;
+    int32_t fine_stride8;
 };
 
 // Complex values per channel-frame in the first pass's output:

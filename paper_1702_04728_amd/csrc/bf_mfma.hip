@@ -168,7 +168,8 @@ void bf_mfma_kernel(LaunchArgs a)
 
     const uint8_t* src = io.in;
     uint2 raw[16];
-    load_block(block_base<kFine>(src, 0), raw, t, block_stride<kFine>());
+    const bool s8 = kFine && a.fine_stride8;
+    load_block(block_base(src, 0, s8), raw, t, block_stride(s8));
 
     float acc[4][2][4];  // [E-W beam j][c = n + 16 nu][d = 4 q + i]
     constexpr int kAcc = sizeof(acc) / sizeof(float);
@@ -186,7 +187,7 @@ void bf_mfma_kernel(LaunchArgs a)
     for (int blk = 0; blk < a.n_blk; ++blk) {
         time_dft_class(wk.s0, raw, s_T, t);
         __syncthreads();
-        if (blk + 1 < a.n_blk) load_block(block_base<kFine>(src, blk + 1), raw, t, block_stride<kFine>());
+        if (blk + 1 < a.n_blk) load_block(block_base(src, blk + 1, s8), raw, t, block_stride(s8));
 
         // E-W phasing straight into stage-1 A fragments: feeds 16 a + n, a = 4q + ia
         half8 A[4][2];

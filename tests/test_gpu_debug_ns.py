@@ -1,0 +1,71 @@
+"""GPU tests of the pre-detection beams (beamform_debug_ns): complex values against
+the oracle's beams before |.|^2, which pins the phases that power parity cannot see,
+and detection of those beams against beamform_frame, for all three precisions."""
+import numpy as np
+import pytest
+
+import synth
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+# amplitude tolerance relative to the largest beam of the same (block, sub-channel):
+# the power tolerances 1e-5 and 2e-3 halved, as amplitudes
+TOL = {"fp32": 5e-6, "fp16": 1e-3, "fp32_mfma": 5e-6}
+PRECISIONS = ["fp32", "fp16", "fp32_mfma"]
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    torch.cuda.init()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bfm():
+    import paper_1702_04728_amd as bf
+    bf.load_library()
+    return bf
+
+
+def _beams(torch_mod, bfm, raw1, freqs, precision):
+    """raw1: one frame [n_chan][384][2048]."""
+    print("debug_ns: %s precision %s" % (raw1.shape, precision), flush=True)
+    with bfm.Beamformer(freqs, precision=precision) as b:
+        d = torch_mod.from_numpy(np.ascontiguousarray(raw1)).cuda()
+        u = b.debug_ns(d)
+        p = b.frame(d[None])
+        torch_mod.cuda.synchronize()
+        return u.cpu().numpy().astype(np.complex128), p.cpu().numpy()[0]
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_complex_beams_against_oracle(torch_mod, bfm, oracle_mod, precision):
+    c = synth.config0()
+    raw1 = np.concatenate([c["raw"][0], synth.uniform_bytes(51, (1, 384, 2048))])
+    freqs = np.array([c["freqs"][0], float(synth.chan_freq_hz(870))])
+    got, _ = _beams(torch_mod, bfm, raw1, freqs, precision)
+    assert got.shape == (2, 24, 16, 2, 4, 256)
+    g = oracle_mod.Geometry()
+    for ch in range(2):
+        ref = oracle_mod.beams_unit(g, freqs[ch], raw1[ch])       # [24][16][2][4][256]
+        scale = np.abs(ref).reshape(24, 16, -1).max(axis=-1)[..., None, None, None]
+        err = (np.abs(got[ch] - ref) / scale).max()
+        print("debug_ns %s channel %d: max |dU| / max|U| per (block, s) %.3e" % (precision, ch, err))
+        assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_detected_beams_equal_frame_output(torch_mod, bfm, precision):
+    raw1 = synth.noise_frames(52, 1, 3)[0]
+    freqs = synth.chan_freq_hz([5, 333, 1010])
+    u, p = _beams(torch_mod, bfm, raw1, freqs, precision)
+    pw = (np.abs(u) ** 2).sum(axis=(1, 3))                          # [ch][s][j][m]
+    for s in range(16):
+        q = (s + 8) % 16
+        ref = p[:, :, q].astype(np.float64).reshape(3, 4, 256)
+        lut = bfm.compute_lut(freqs)
+        # outputs gather bins through the Eq. (1) table; the beams hold them per m
+        assert np.allclose(pw[:, s], ref, rtol=1e-5, atol=0), (s, lut.shape)

@@ -45,7 +45,10 @@ MUTANTS = [
     ("power drops imaginary part",
      "u[2 * s] * u[2 * s] + u[2 * s + 1] * u[2 * s + 1];", "u[2 * s] * u[2 * s];"),
     ("last block not integrated",
-     "for (int32_t blk = 0; blk < T / L; ++blk) {", "for (int32_t blk = 0; blk < T / L - 1; ++blk) {"),
+     "                for (int32_t blk = 0; blk < T / L; ++blk) {\n                    size_t ob = (((size_t)p * NJ + j) * NM + m) * T + (size_t)blk * L;\n                    orc_upchan_tab(L, roots_l, &B[2 * ob], u);\n                    for (int32_t s = 0; s < L; ++s) {\n                        int32_t q",
+     "                for (int32_t blk = 0; blk < T / L - 1; ++blk) {\n                    size_t ob = (((size_t)p * NJ + j) * NM + m) * T + (size_t)blk * L;\n                    orc_upchan_tab(L, roots_l, &B[2 * ob], u);\n                    for (int32_t s = 0; s < L; ++s) {\n                        int32_t q"),
+    ("complex beams written conjugated",
+     "                        out[2 * o + 1] = u[2 * s + 1];", "                        out[2 * o + 1] = -u[2 * s + 1];"),
     ("one polarisation only",
      "            for (int32_t p = 0; p < NP; ++p)\n                for (int32_t blk",
      "            for (int32_t p = 0; p < 1; ++p)\n                for (int32_t blk"),

@@ -246,6 +246,42 @@ def test_pipeline_tiny_brute_force(oracle_mod):
     np.testing.assert_allclose(out, ref, rtol=1e-12, atol=1e-9)
 
 
+def test_complex_beams_tiny_brute_force(oracle_mod):
+    """The pre-detection beams (complex, before |.|^2) against the same unstaged sum:
+    this pins the phases, which detection discards."""
+    kw = dict(n_feed=4, pad=2, n_cyl=2, n_pol=2, n_beam_ns=3, n_beam_ew=2, n_dft=4, n_time=8)
+    cyl_x = np.array([-10.0, 10.0])
+    sin_theta = np.array([-0.3, 0.05, 0.6])
+    sin_phi = np.array([-0.004, 0.007])
+    g = oracle_mod.Geometry(**kw, cyl_x_m=cyl_x, sin_theta_ns=sin_theta, sin_phi_ew=sin_phi)
+    f = 700e6
+    raw = synth.uniform_bytes(13, (8, 16))
+    got = oracle_mod.beams_unit(g, f, raw)                    # [blk][s][p][j][m]
+    k = [math.floor(8 * f * D / C0 * st + 0.5) % 8 for st in sin_theta]
+    ref = np.zeros_like(got)
+    for blk in range(2):
+        for s in range(4):
+            for p in range(2):
+                for j in range(2):
+                    for m in range(3):
+                        acc = 0j
+                        for tau in range(4):
+                            for c in range(2):
+                                for n in range(4):
+                                    byte = int(raw[blk * 4 + tau, (c * 4 + n) * 2 + p])
+                                    xv = complex((byte >> 4) - 8, (byte & 15) - 8)
+                                    ph = -(n * k[m] / 8 + f * cyl_x[c] * sin_phi[j] / C0 + s * tau / 4)
+                                    acc += xv * complex(math.cos(2 * math.pi * ph),
+                                                        math.sin(2 * math.pi * ph))
+                        ref[blk, s, p, j, m] = acc
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-9)
+    # detection of these beams is the pipeline's output
+    pw = (np.abs(got) ** 2).sum(axis=(0, 2))                   # [s][j][m]
+    out = oracle_mod.beamform_unit(g, f, raw)                  # [j*3+m][q]
+    for s in range(4):
+        assert np.allclose(out[:, (s + 2) % 4], pw[s].reshape(-1), rtol=1e-12)
+
+
 def test_pipeline_energy_even_odd_bins(oracle_mod):
     """Run once keeping the 256 even bins and once the 256 odd bins, with the
     scaled-unitary E-W directions: the summed output equals 16 * 4 * 512 * sum|x|^2
