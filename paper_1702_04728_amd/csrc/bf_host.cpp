@@ -318,6 +318,13 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
             const double a = kTwoPi * (double)r / (double)bf::kBins;
             tw[c * 16 + b] = make_float2((float)std::cos(a), (float)-std::sin(a));
         }
+    // w128^(u k) of the 128-point up-channelisation's second pass
+    std::vector<float2> tw128(128);
+    for (int u = 0; u < 8; ++u)
+        for (int k = 0; k < 16; ++k) {
+            const double a = kTwoPi * (double)(u * k) / 128.0;
+            tw128[u * 16 + k] = make_float2((float)std::cos(a), (float)-std::sin(a));
+        }
 
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { int32_t r = hip_fail(nullptr, e, "hipGetDevice"); delete p; return r; }
@@ -329,7 +336,8 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
     if ((e = hipMalloc(&p->d_lut, lut_b)) != hipSuccess ||
         (e = hipMalloc(&p->d_ew, ew_b)) != hipSuccess ||
         (e = hipMalloc(&p->d_tw, tw_b)) != hipSuccess ||
-        (e = hipMalloc(&p->d_mf, mf.size())) != hipSuccess) {
+        (e = hipMalloc(&p->d_mf, mf.size())) != hipSuccess ||
+        (e = hipMalloc(&p->d_tw128, tw128.size() * sizeof(float2))) != hipSuccess) {
         int32_t r = fail(nullptr, BF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
         beamform_destroy(p);
         return r;
@@ -338,6 +346,8 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
         (e = hipMemcpyAsync(p->d_ew, ew.data(), ew_b, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(p->d_tw, tw.data(), tw_b, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(p->d_mf, mf.data(), mf.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(p->d_tw128, tw128.data(), tw128.size() * sizeof(float2),
+                            hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess) {
         int32_t r = hip_fail(nullptr, e, "table upload");
         beamform_destroy(p);
@@ -383,19 +393,6 @@ int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_fram
         return fail(p, BF_E_UNSUPPORTED, "the 128-point up-channelisation needs n_time % 128 == 0");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    if (!p->d_tw128) {
-        std::vector<float2> tw(128);
-        for (int u = 0; u < 8; ++u)
-            for (int k = 0; k < 16; ++k) {
-                const double a = kTwoPi * (double)(u * k) / 128.0;
-                tw[u * 16 + k] = make_float2((float)std::cos(a), (float)-std::sin(a));
-            }
-        if ((e = hipMalloc(&p->d_tw128, 128 * sizeof(float2))) != hipSuccess)
-            return fail(p, BF_E_NOMEM, "w128 table");
-        if ((e = hipMemcpy(p->d_tw128, tw.data(), 128 * sizeof(float2), hipMemcpyHostToDevice)) !=
-            hipSuccess)
-            return hip_fail(p, e, "w128 table upload");
-    }
     // whole frames per chunk (so a channel-frame's tables are its row mod
     // n_chan), about 256 channel-frames of first-pass output at a time
     const int32_t n_it = p->cfg.n_time / bf::kUp;
