@@ -86,6 +86,21 @@ __device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d)
     d = csub(t1, rot<1>(t3));
 }
 
+// Byte k (0..3, a compile-time constant after unrolling) of x as a float: one
+// v_cvt_f32_ubyteN.  Kept opaque so that a following exact "- 32.f" is not
+// turned into integer arithmetic (mask, subtract, convert: three instructions).
+__device__ __forceinline__ float ubyte_to_float(uint32_t x, int k)
+{
+    float r;
+    switch (k) {
+    case 0: asm("v_cvt_f32_ubyte0 %0, %1" : "=v"(r) : "v"(x)); break;
+    case 1: asm("v_cvt_f32_ubyte1 %0, %1" : "=v"(r) : "v"(x)); break;
+    case 2: asm("v_cvt_f32_ubyte2 %0, %1" : "=v"(r) : "v"(x)); break;
+    default: asm("v_cvt_f32_ubyte3 %0, %1" : "=v"(r) : "v"(x)); break;
+    }
+    return r;
+}
+
 // Orders LDS traffic between the lanes of one wavefront.
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -215,16 +230,23 @@ __device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restr
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             const int e = 2 * h + p;  // input 8t + e: feed 4 (t % 64) + h, pol p
-            const int w = e >> 2, sh = 8 * (e & 3);
+            const int w = e >> 2;
+            // each byte is value + 32 (both components)
+            constexpr float kOff = S0 == 0 ? 0.f : 32.f;
             float2 y[4];
 #pragma unroll
             for (int t1 = 0; t1 < 4; ++t1)
-                y[t1] = make_float2((float)((yr[t1][w] >> sh) & 0xffu) - 32.f,
-                                    (float)((yi[t1][w] >> sh) & 0xffu) - 32.f);
+                y[t1] = make_float2(ubyte_to_float(yr[t1][w], e & 3) - kOff,
+                                    ubyte_to_float(yi[t1][w], e & 3) - kOff);
             y[1] = tw16<S0>(y[1]);
             y[2] = tw16<2 * S0>(y[2]);
             y[3] = tw16<3 * S0>(y[3]);
             dft4(y[0], y[1], y[2], y[3]);
+            if constexpr (S0 == 0) {
+                // no twiddles: the offset reaches only bin 0, as 4 x 32, and every
+                // value here is an integer far below 2^24, so this is exact
+                y[0] = make_float2(y[0].x - 128.f, y[0].y - 128.f);
+            }
 #pragma unroll
             for (int s2 = 0; s2 < 4; ++s2) o[p][s2] = y[s2];
         }

@@ -22,14 +22,18 @@
 //   A  each thread reads 16 samples of 8 consecutive inputs, forms its four
 //      time-DFT outputs via a radix-4 split (a DFT-4 over the sample stride,
 //      a twiddle, a DFT-4 over the sample phase), writes them to LDS;
-//   B1 each 16-lane group (s2, j) applies E-W weights W[j][c] while reading
-//      the two polarisation lines it owns (lane b holds feeds 16a + b);
-//   B2 each group transforms both lines: 512 = 32 x 16 with the upper half of
-//      the input zero, so step 1 is a pruned 32-point DFT per lane (two 16-point
-//      FFTs), then twiddles w512^(b c), a 16-lane transpose through LDS and a
-//      16-point FFT per lane; |X|^2 of both pols accumulates in registers.
-// After the last block, per-bin powers go through LDS and are gathered by
-// the bin table into out[beam][q].
+//   B1 each 16-lane group (s2, jp, p) forms the E-W beams j = jp and 3 - jp
+//      of polarisation p while reading its lines (lane b holds feeds 16a + b).
+//      With the mirror-symmetric default geometry the pair shares its sums:
+//      S_c = y_c + y_(3-c), D_c = y_c - y_(3-c), beam jp = P + iQ and beam
+//      3 - jp = P - iQ with P = sum_c Re W[jp][c] S_c, Q = sum_c Im W[jp][c] D_c
+//      (c = 0, 1), 20 instead of 32 operations per feed and pair;
+//   B2 each group transforms its two lines: 512 = 32 x 16 with the upper half
+//      of the input zero, so step 1 is a pruned 32-point DFT per lane (two
+//      16-point FFTs), then twiddles w512^(b c), a 16-lane transpose through LDS
+//      and a 16-point FFT per lane; |X|^2 accumulates in registers per line.
+// After the last block the two polarisations' per-bin powers are summed in
+// LDS and gathered by the bin table into out[beam][q].
 #include <hip/hip_runtime.h>
 
 #include "bf_device.h"
@@ -83,7 +87,7 @@ template <bool kFine>
 __device__ __forceinline__ void ns_line_power(const float2 (&x)[16], float (&acc)[2][16],
                                               float2* __restrict__ bufE,
                                               float2* __restrict__ bufO,
-                                              const float2* __restrict__ tw, int b,
+                                              const float4* __restrict__ tw, int b,
                                               const int32_t* __restrict__ lut = nullptr,
                                               float2* __restrict__ fine_dst = nullptr)
 {
@@ -109,11 +113,25 @@ __device__ __forceinline__ void ns_line_power(const float2 (&x)[16], float (&acc
     // step 1: Z[2c'] = E[c'], Z[2c'+1] = O[c'] is the pruned 32-point DFT over a
     fft16(E);
     fft16(O);
-    // step 2: Z[c] *= w512^(b c); step 3a: transpose through LDS
+    // step 2: Z[c] *= w512^(b c) (tw[c' * 16 + b] holds the twiddles of bins
+    // 2 c' and 2 c' + 1); step 3a: transpose through LDS
+    // (twiddles read in batches of four, each issued a batch ahead of use)
+    float4 w[2][4];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        bufE[c * kXpStride + b] = cmul(E[c], tw[(2 * c) * 16 + b]);
-        bufO[c * kXpStride + b] = cmul(O[c], tw[(2 * c + 1) * 16 + b]);
+    for (int i = 0; i < 4; ++i) w[0][i] = tw[i * 16 + b];
+#pragma unroll
+    for (int c4 = 0; c4 < 4; ++c4) {
+        if (c4 < 3) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) w[(c4 + 1) & 1][i] = tw[(4 * (c4 + 1) + i) * 16 + b];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int c = 4 * c4 + i;
+            const float4 wc = w[c4 & 1][i];
+            bufE[c * kXpStride + b] = cmul(E[c], make_float2(wc.x, wc.y));
+            bufO[c * kXpStride + b] = cmul(O[c], make_float2(wc.z, wc.w));
+        }
     }
     wave_lds_sync();
 #pragma unroll
@@ -145,28 +163,36 @@ __device__ __forceinline__ void ns_line_power(const float2 (&x)[16], float (&acc
 }
 static_assert(2 * kXpBuf >= 512, "a group's transpose buffers must hold one line's bins");
 
-template <bool kFine>
+template <bool kSym, bool kFine>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bf_fp32_kernel(LaunchArgs a)
 {
     __shared__ __align__(16) float2 s_union[kUnionF2];
-    __shared__ __align__(16) float2 s_tw[32 * 16];
+    __shared__ __align__(16) float4 s_tw[16 * 16];  // [c'][b]: w512^(b 2c'), w512^(b (2c'+1))
 
     const Work wk = work_of_block();
     UnitIO io;
     if (!resolve_unit(a, wk, io)) return;
     const int t = threadIdx.x;
-    const int g = t >> 4;      // group: s2 = g >> 2 (= wave), j = g & 3
+    const int g = t >> 4;      // group: s2 = g >> 2 (= wave), jp = (g >> 1) & 1, p = g & 1
     const int b = t & 15;
-    const int s2 = g >> 2, j = g & 3;
+    const int s2 = g >> 2, jp = (g >> 1) & 1, pol = g & 1;
+    const int jl[2] = {jp, 3 - jp};  // the group's two E-W beams
 
-    for (int i = t; i < 32 * 16; i += kThreads) s_tw[i] = a.tw[i];
-    float2 W[4];
+    {
+        const int c2 = t >> 4, bb = t & 15;
+        const float2 w0 = a.tw[(2 * c2) * 16 + bb], w1 = a.tw[(2 * c2 + 1) * 16 + bb];
+        s_tw[t] = make_float4(w0.x, w0.y, w1.x, w1.y);
+    }
+    float2 W[2][4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) W[c] = a.ew[((size_t)io.ew_row * kBeamEW + j) * kCyl + c];
+    for (int l = 0; l < 2; ++l)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) W[l][c] = a.ew[((size_t)io.ew_row * kBeamEW + jl[l]) * kCyl + c];
 
     const uint8_t* src = io.in;
     float4* T = reinterpret_cast<float4*>(s_union);
+    const float2* Tp = reinterpret_cast<const float2*>(s_union) + pol;  // this pol of T
     float2* bufE = s_union + g * 2 * kXpBuf;
     float2* bufO = bufE + kXpBuf;
 
@@ -174,62 +200,92 @@ void bf_fp32_kernel(LaunchArgs a)
     const bool s8 = kFine && a.fine_stride8;
     load_block(block_base(src, 0, s8), raw, t, block_stride(s8));
 
-    float acc[2][16];
+    float acc[2][2][16];  // [line l: beam jl[l]][E/O][d]
     constexpr int kAcc = sizeof(acc) / sizeof(float);
     if (io.first) {
 #pragma unroll
-        for (int d = 0; d < 16; ++d) acc[0][d] = acc[1][d] = 0.f;
+        for (int l = 0; l < 2; ++l)
+#pragma unroll
+            for (int d = 0; d < 16; ++d) acc[l][0][d] = acc[l][1][d] = 0.f;
     } else {
-        load_partial<kAcc>(&acc[0][0], io.partial, t);
+        load_partial<kAcc>(&acc[0][0][0], io.partial, t);
     }
 
     for (int blk = 0; blk < a.n_blk; ++blk) {
         // A: time DFT of this thread's 8 inputs
         time_dft_class(wk.s0, raw, T, t);
         __syncthreads();
-        // prefetch the next block's samples while the transforms run
-        if (blk + 1 < a.n_blk) load_block(block_base(src, blk + 1, s8), raw, t, block_stride(s8));
-        // B1: E-W phasing while loading this group's two lines (feeds 16 a + b)
+        // B1: E-W phasing while loading this group's feeds 16 a + b of pol p
         float2 v0[16], v1[16];
 #pragma unroll
         for (int aa = 0; aa < 16; ++aa) {
-            float2 p0 = make_float2(0.f, 0.f), p1 = make_float2(0.f, 0.f);
+            float2 y[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const float4 q = T[s2 * 1024 + c * 256 + 16 * aa + b];
-                p0 = cmac(p0, make_float2(q.x, q.y), W[c]);
-                p1 = cmac(p1, make_float2(q.z, q.w), W[c]);
+            for (int c = 0; c < 4; ++c) y[c] = Tp[2 * (s2 * 1024 + c * 256 + 16 * aa + b)];
+            if constexpr (kSym) {
+                const float2 S0 = cadd(y[0], y[3]), S1 = cadd(y[1], y[2]);
+                const float2 D0 = csub(y[0], y[3]), D1 = csub(y[1], y[2]);
+                const float2 P = make_float2(fmaf(W[0][0].x, S0.x, W[0][1].x * S1.x),
+                                             fmaf(W[0][0].x, S0.y, W[0][1].x * S1.y));
+                const float2 Q = make_float2(fmaf(W[0][0].y, D0.x, W[0][1].y * D1.x),
+                                             fmaf(W[0][0].y, D0.y, W[0][1].y * D1.y));
+                v0[aa] = make_float2(P.x - Q.y, P.y + Q.x);
+                v1[aa] = make_float2(P.x + Q.y, P.y - Q.x);
+            } else {
+                float2 p0 = make_float2(0.f, 0.f), p1 = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    p0 = cmac(p0, y[c], W[0][c]);
+                    p1 = cmac(p1, y[c], W[1][c]);
+                }
+                v0[aa] = p0;
+                v1[aa] = p1;
             }
-            v0[aa] = p0;
-            v1[aa] = p1;
         }
         __syncthreads();
-        // B2: N-S transform of both polarisations, power into per-bin accumulators
-        if constexpr (kFine) {
-            const int32_t* lut = a.lut + (size_t)io.row * kBeamNS;
-            const int k = wk.s0 + 4 * s2;
-            ns_line_power<true>(v0, acc, bufE, bufO, s_tw, b, lut, fine_line_ptr(a, wk.unit, blk, k, j));
-            ns_line_power<true>(v1, acc, bufE, bufO, s_tw, b, lut, fine_line_ptr(a, wk.unit, blk, k, 4 + j));
-        } else {
-            ns_line_power<false>(v0, acc, bufE, bufO, s_tw, b);
-            ns_line_power<false>(v1, acc, bufE, bufO, s_tw, b);
-        }
+        // B2: N-S transform of both lines, power into per-bin accumulators; the
+        // next block's samples are fetched during the second line (issued
+        // there, the 32 registers they take are free for E-W phasing and the
+        // first line).  The last block fetches itself again rather than
+        // branch: one basic block schedules with fewer live registers.
+        const int32_t* lut = kFine ? a.lut + (size_t)io.row * kBeamNS : nullptr;
+        const int k = wk.s0 + 4 * s2;
+        ns_line_power<kFine>(v0, acc[0], bufE, bufO, s_tw, b, lut,
+                             kFine ? fine_line_ptr(a, wk.unit, blk, k, pol * 4 + jl[0]) : nullptr);
+        load_block(block_base(src, min(blk + 1, a.n_blk - 1), s8), raw, t, block_stride(s8));
+        ns_line_power<kFine>(v1, acc[1], bufE, bufO, s_tw, b, lut,
+                             kFine ? fine_line_ptr(a, wk.unit, blk, k, pol * 4 + jl[1]) : nullptr);
         __syncthreads();
     }
     if constexpr (kFine) return;  // the second pass detects and integrates
 
     if (!io.last) {  // frame continues in the next chunk's launch
-        store_partial<kAcc>(&acc[0][0], io.partial, t);
+        store_partial<kAcc>(&acc[0][0][0], io.partial, t);
         return;
     }
-    // per-bin powers -> LDS, then gather by the bin table into out[beam][q]
+    // per-bin powers -> LDS (pol 0 writes, pol 1 adds), then gather by the bin
+    // table into out[beam][q]
     float* P = reinterpret_cast<float*>(s_union);
 #pragma unroll
-    for (int d = 0; d < 16; ++d) {
-        P[g * 512 + 2 * b + 32 * d] = acc[0][d];
-        P[g * 512 + 2 * b + 1 + 32 * d] = acc[1][d];
+    for (int ph = 0; ph < 2; ++ph) {
+        if (pol == ph) {
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                float* row = P + (s2 * 4 + jl[l]) * 512 + 2 * b;
+#pragma unroll
+                for (int d = 0; d < 16; ++d) {
+                    if (ph == 0) {
+                        row[32 * d] = acc[l][0][d];
+                        row[32 * d + 1] = acc[l][1][d];
+                    } else {
+                        row[32 * d] += acc[l][0][d];
+                        row[32 * d + 1] += acc[l][1][d];
+                    }
+                }
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
     write_output(P, a, io, wk.s0, t);
 }
 
@@ -240,8 +296,13 @@ hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream)
     if (a.n_units <= 0) return hipSuccess;
     LaunchArgs args = a;
     void* params[] = {&args};
-    const void* k = a.fine ? reinterpret_cast<const void*>(&bf_fp32_kernel<true>)
-                           : reinterpret_cast<const void*>(&bf_fp32_kernel<false>);
+    const void* k;
+    if (a.fine)
+        k = a.sym_ew ? reinterpret_cast<const void*>(&bf_fp32_kernel<true, true>)
+                     : reinterpret_cast<const void*>(&bf_fp32_kernel<false, true>);
+    else
+        k = a.sym_ew ? reinterpret_cast<const void*>(&bf_fp32_kernel<true, false>)
+                     : reinterpret_cast<const void*>(&bf_fp32_kernel<false, false>);
     return hipLaunchKernel(k, dev::grid_for(a.n_units), dim3(dev::kThreads), params, 0, stream);
 }
 
