@@ -292,14 +292,24 @@ __device__ __forceinline__ int block_stride(bool stride8)
 
 // Complex beams out (first pass of the 128-point up-channelisation, or the
 // pre-detection beams): the 512 bins of one line (sub-channel k, line
-// p * 4 + j, block iteration it) sit in LDS at bins[];
-// the kept beam of every N-S pointing m is bins[lut[m]].  Lanes `lane` of
-// `n_lanes` write consecutive m.
-__device__ __forceinline__ void write_fine_line(const float2* __restrict__ bins,
-                                                const int32_t* __restrict__ lut,
-                                                float2* __restrict__ dst, int lane, int n_lanes)
+// p * 4 + j, block iteration it) sit in LDS at bins[]; the kept beam of every
+// N-S pointing m is bins[lut[m]].  Lane `lane` of 256 / N lanes writes the
+// beams m = lane + (256 / N) i, i < N, whose table entries it holds in
+// registers (read once per kernel by load_lut_lane): a table read inside the
+// line loop would wait, through the shared load/store counter, for every
+// beam store issued before it.
+template <int N>
+__device__ __forceinline__ void load_lut_lane(const int32_t* __restrict__ lut, int32_t (&lv)[N], int lane)
 {
-    for (int m = lane; m < kBeamNS; m += n_lanes) dst[m] = bins[lut[m]];
+#pragma unroll
+    for (int i = 0; i < N; ++i) lv[i] = lut[lane + (kBeamNS / N) * i];
+}
+template <int N>
+__device__ __forceinline__ void write_fine_line(const float2* __restrict__ bins, const int32_t (&lv)[N],
+                                                float2* __restrict__ dst, int lane)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) dst[lane + (kBeamNS / N) * i] = bins[lv[i]];
 }
 __device__ __forceinline__ float2* fine_line_ptr(const LaunchArgs& a, int unit, int it, int k, int line)
 {

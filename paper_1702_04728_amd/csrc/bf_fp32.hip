@@ -88,8 +88,8 @@ __device__ __forceinline__ void ns_line_power(const float2 (&x)[16], float (&acc
                                               float2* __restrict__ bufE,
                                               float2* __restrict__ bufO,
                                               const float4* __restrict__ tw, int b,
-                                              const int32_t* __restrict__ lut = nullptr,
-                                              float2* __restrict__ fine_dst = nullptr)
+                                              const int32_t (&lv)[kFine ? 16 : 1],
+                                              float2* __restrict__ fine_dst)
 {
     float2 E[16], O[16];
 #pragma unroll
@@ -151,7 +151,7 @@ __device__ __forceinline__ void ns_line_power(const float2 (&x)[16], float (&acc
             bins[2 * b + 1 + 32 * d] = O[d];
         }
         wave_lds_sync();
-        write_fine_line(bins, lut, fine_dst, b, 16);
+        write_fine_line<16>(bins, lv, fine_dst, b);
         wave_lds_sync();
     } else {
 #pragma unroll
@@ -195,6 +195,9 @@ void bf_fp32_kernel(LaunchArgs a)
     const float2* Tp = reinterpret_cast<const float2*>(s_union) + pol;  // this pol of T
     float2* bufE = s_union + g * 2 * kXpBuf;
     float2* bufO = bufE + kXpBuf;
+
+    int32_t lv[kFine ? 16 : 1] = {};  // bin-table entries of the beams this lane writes
+    if constexpr (kFine) load_lut_lane<16>(a.lut + (size_t)io.row * kBeamNS, lv, b);
 
     uint2 raw[16];
     const bool s8 = kFine && a.fine_stride8;
@@ -248,12 +251,11 @@ void bf_fp32_kernel(LaunchArgs a)
         // there, the 32 registers they take are free for E-W phasing and the
         // first line).  The last block fetches itself again rather than
         // branch: one basic block schedules with fewer live registers.
-        const int32_t* lut = kFine ? a.lut + (size_t)io.row * kBeamNS : nullptr;
         const int k = wk.s0 + 4 * s2;
-        ns_line_power<kFine>(v0, acc[0], bufE, bufO, s_tw, b, lut,
+        ns_line_power<kFine>(v0, acc[0], bufE, bufO, s_tw, b, lv,
                              kFine ? fine_line_ptr(a, wk.unit, blk, k, pol * 4 + jl[0]) : nullptr);
         load_block(block_base(src, min(blk + 1, a.n_blk - 1), s8), raw, t, block_stride(s8));
-        ns_line_power<kFine>(v1, acc[1], bufE, bufO, s_tw, b, lut,
+        ns_line_power<kFine>(v1, acc[1], bufE, bufO, s_tw, b, lv,
                              kFine ? fine_line_ptr(a, wk.unit, blk, k, pol * 4 + jl[1]) : nullptr);
         __syncthreads();
     }

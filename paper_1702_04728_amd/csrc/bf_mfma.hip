@@ -166,6 +166,9 @@ void bf_mfma_kernel(LaunchArgs a)
 #pragma unroll
         for (int c = 0; c < 4; ++c) W[j][c] = a.ew[((size_t)io.ew_row * kBeamEW + j) * kCyl + c];
 
+    int32_t lv[kFine ? 4 : 1] = {};  // bin-table entries of the beams this lane writes
+    if constexpr (kFine) load_lut_lane<4>(a.lut + (size_t)io.row * kBeamNS, lv, lane);
+
     const uint8_t* src = io.in;
     uint2 raw[16];
     const bool s8 = kFine && a.fine_stride8;
@@ -283,8 +286,8 @@ void bf_mfma_kernel(LaunchArgs a)
                 }
                 if constexpr (kFine) {
                     wave_lds_sync();
-                    write_fine_line(s_bins + s2 * 512, a.lut + (size_t)io.row * kBeamNS,
-                                    fine_line_ptr(a, wk.unit, blk, wk.s0 + 4 * s2, p * 4 + j), lane, 64);
+                    write_fine_line<4>(s_bins + s2 * 512, lv,
+                                       fine_line_ptr(a, wk.unit, blk, wk.s0 + 4 * s2, p * 4 + j), lane);
                     wave_lds_sync();
                 }
             }
