@@ -181,6 +181,12 @@ __device__ __forceinline__ void store_partial(const float* acc, float* __restric
     for (int e = 0; e < N; ++e) p[e * kThreads + t] = acc[e];
 }
 
+// LDS position (in float4) of time-DFT slot sigma = cyl * 256 + feed: bits 4-5
+// are XORed into bits 0-1.  The time DFT writes slots 4 t + h (lane stride 4)
+// and E-W phasing reads 16 consecutive slots; with the swizzle both touch 16
+// distinct 16-byte bank groups per 16 lanes, without it the writes hit 4.
+__device__ __forceinline__ int tslot(int sigma) { return sigma ^ ((sigma >> 4) & 3); }
+
 // One 16-sample block of this thread's 8 inputs (bytes 8t .. 8t+7 of each
 // sample): time-DFT bins s = S0 + 4 s2, s2 = 0..3, by a radix-4 split of the
 // 16-point DFT:
@@ -188,7 +194,7 @@ __device__ __forceinline__ void store_partial(const float* acc, float* __restric
 //   T[s2] = sum_t1 (y[t1] w16^(t1 S0)) (-i)^(t1 s2)
 // y is formed on the raw nibbles four inputs at a time (bytewise integer
 // sums in a 32-bit word, biased so no byte borrows), converted to float once.
-// Output: T[s2 * 1024 + slot], slot = cyl * 256 + feed, float4 = both pols.
+// Output: T[s2 * 1024 + tslot(slot)], slot = cyl * 256 + feed, float4 = both pols.
 template <int S0>
 __device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restrict__ T, int t)
 {
@@ -252,7 +258,7 @@ __device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restr
         }
 #pragma unroll
         for (int s2 = 0; s2 < 4; ++s2)
-            T[s2 * 1024 + 4 * t + h] = make_float4(o[0][s2].x, o[0][s2].y, o[1][s2].x, o[1][s2].y);
+            T[s2 * 1024 + tslot(4 * t + h)] = make_float4(o[0][s2].x, o[0][s2].y, o[1][s2].x, o[1][s2].y);
     }
 }
 

@@ -45,7 +45,10 @@ using namespace dev;
 
 constexpr int kXpStride = 17;                    // padded row of a transpose buffer
 constexpr int kXpBuf = 16 * kXpStride;           // float2 per buffer
-constexpr int kUnionF2 = 16 * 2 * kXpBuf;        // 16 groups x {E, O} buffers (8704)
+// a group's {E, O} buffers plus 16 float2, so that consecutive groups start
+// 32 banks apart (1120 words, not a multiple of 64)
+constexpr int kGroupF2 = 2 * kXpBuf + 16;
+constexpr int kUnionF2 = 16 * kGroupF2;          // 16 groups (8960 float2)
 constexpr int kTF4 = 4 * 1024;                   // time-DFT output: 4 s2 x 1024 float4
 static_assert(kUnionF2 * 8 >= kTF4 * 16, "union region must hold the time-DFT output");
 static_assert(kUnionF2 * 8 >= 16 * 512 * 4, "union region must hold the per-bin powers");
@@ -194,7 +197,7 @@ void bf_fp32_kernel(LaunchArgs a)
     const uint8_t* src = io.in;
     float4* T = reinterpret_cast<float4*>(s_union);
     const float2* Tp = reinterpret_cast<const float2*>(s_union) + pol;  // this pol of T
-    float2* bufE = s_union + g * 2 * kXpBuf;
+    float2* bufE = s_union + g * kGroupF2;
     float2* bufO = bufE + kXpBuf;
 
     int32_t lv[kFine ? 16 : 1] = {};  // bin-table entries of the beams this lane writes
@@ -225,7 +228,7 @@ void bf_fp32_kernel(LaunchArgs a)
         for (int aa = 0; aa < 16; ++aa) {
             float2 y[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) y[c] = Tp[2 * (s2 * 1024 + c * 256 + 16 * aa + b)];
+            for (int c = 0; c < 4; ++c) y[c] = Tp[2 * (s2 * 1024 + tslot(c * 256 + 16 * aa + b))];
             if constexpr (kSym) {
                 const float2 S0 = cadd(y[0], y[3]), S1 = cadd(y[1], y[2]);
                 const float2 D0 = csub(y[0], y[3]), D1 = csub(y[1], y[2]);

@@ -202,7 +202,7 @@ void bf_mfma_kernel(LaunchArgs a)
                 float2 y0[4], y1[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const float4 x4 = s_T[s2 * 1024 + c * 256 + 16 * (4 * q + ia) + n];
+                    const float4 x4 = s_T[s2 * 1024 + tslot(c * 256 + 16 * (4 * q + ia) + n)];
                     y0[c] = make_float2(x4.x, x4.y);
                     y1[c] = make_float2(x4.z, x4.w);
                 }
@@ -225,7 +225,7 @@ void bf_mfma_kernel(LaunchArgs a)
                     float2 y[4];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
-                        const float4 x4 = s_T[s2 * 1024 + c * 256 + 16 * (4 * q + ia) + n];
+                        const float4 x4 = s_T[s2 * 1024 + tslot(c * 256 + 16 * (4 * q + ia) + n)];
                         y[c] = p ? make_float2(x4.z, x4.w) : make_float2(x4.x, x4.y);
                     }
                     ew_phase<kSym>(y, W, v, ia);
