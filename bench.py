@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -68,10 +69,13 @@ def log(*a):
 
 
 def source_hash(path_key: str) -> str:
+    """SHA-256 over the kernel sources with comments and whitespace removed: a
+    comment edit leaves the recorded counters valid, any code change voids them."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES[path_key]:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            text = re.sub(r"//[^\n]*|/\*.*?\*/", " ", f.read(), flags=re.S)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -81,8 +81,9 @@ struct LaunchArgs {
     int32_t fine_half;
 };
 // Exact power-of-two scale of FP16 complex beams: the largest beam a channel-
-// frame can produce (16 x 8 x 4 x 256 = 131072 in amplitude) stays below the
-// FP16 maximum, and noise beams stay normal numbers.
+// frame can produce (|x| <= 8 sqrt 2 per sample; x 16 samples x 4 cylinders x
+// 256 feeds < 2^18 in amplitude) stays below the FP16 maximum (65504), and
+// noise beams stay normal numbers.
 constexpr float kFineHalfScale = 1.0f / 256.0f;
 
 // Complex values per channel-frame in the first pass's output:

@@ -110,6 +110,26 @@ def test_closed_form_relations_to_16_point(torch_mod, bfm):
     assert np.allclose(t128, 8 * t16, rtol=TOL, atol=0)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp32_mfma"])
+def test_full_scale_coherent_input(torch_mod, bfm, oracle_mod, precision):
+    """Every input at the most negative code (-8 - 8i) in every sample: the largest
+    beams any frame can produce (N-S bin 0 of a coherent line, about 2^17.5 in
+    amplitude before detection), all in the channel-centre sub-channel.  The FP16
+    path's scaled FP16-pair intermediate must neither overflow nor lose them; the
+    other sub-channels stay at rounding level."""
+    raw = np.zeros((1, 2, 384, 2048), np.uint8)
+    freqs = synth.chan_freq_hz([20, 1000])
+    got = _run(torch_mod, bfm, raw, freqs, 128, precision=precision)
+    assert np.isfinite(got).all()
+    ref = oracle_mod.beamform_upchan128(oracle_mod.Geometry(), freqs, raw)
+    big = ref >= 1e-3 * ref.max()
+    err = np.abs(got[big] - ref[big]) / ref[big]
+    print("upchan128 full scale %s: max rel err %.3e over %d outputs" % (precision, err.max(), big.sum()))
+    assert err.max() <= TOLS[precision]
+    assert big[..., 8].any() and not big[..., np.arange(16) != 8].any()
+    assert np.abs(got[..., np.arange(16) != 8]).max() <= 1e-5 * ref.max()
+
+
 def test_unsupported_configurations(torch_mod, bfm):
     short = torch_mod.zeros((1, 1, 48, 2048), dtype=torch_mod.uint8, device="cuda")
     with bfm.Beamformer([600e6], n_time=48) as b:
