@@ -201,19 +201,28 @@ def config1_data():
     return synth.config1()
 
 
+@pytest.fixture(scope="module")
+def config1_ref(oracle_mod, config1_data):
+    """The oracle on every channel-frame of the benchmark workload (512 channel-frames,
+    about 7 s on 16 host threads), shared by the three precisions."""
+    c = config1_data
+    return oracle_mod.beamform(oracle_mod.Geometry(), c["freqs"], c["raw"])
+
+
 @pytest.mark.parametrize("precision", PRECISIONS)
-def test_config1_full_size_sampled(torch_mod, bfm, oracle_mod, config1_data, precision):
-    """The benchmark workload at full size (4 channels x 128 frames, one launch):
-    sampled channel-frames against the oracle, every output finite and positive."""
+def test_config1_full_size_all_outputs(torch_mod, bfm, config1_data, config1_ref, precision):
+    """The benchmark workload at full size (4 channels x 128 frames, one launch, as the
+    bench times it) against the oracle on every one of its 8.4 M outputs: the
+    per-output relative power error distribution (the FP16-MFMA row is the
+    workload's FP16 form)."""
     c = config1_data
     got = _run(torch_mod, bfm, c["raw"], c["freqs"], precision=precision)
     assert np.all(np.isfinite(got)) and np.all(got > 0)
-    units = [(0, 0), (0, 3), (37, 1), (64, 2), (101, 0), (127, 3)]
-    ref = oracle_mod.beamform(oracle_mod.Geometry(), c["freqs"], c["raw"], units=units)
-    for u, (f, ch) in enumerate(units):
-        err = _rel(got[f, ch], ref[u])
-        print("config1 %s unit (%d, %d) max rel err %.3e" % (precision, f, ch, err.max()))
-        assert err.max() <= TOL[precision], (f, ch, err.max())
+    err = _rel(got, config1_ref)
+    p99, p999 = np.quantile(err, [0.99, 0.999])
+    print("config1 all %d outputs %s: max %.3e p99.9 %.3e p99 %.3e mean %.3e"
+          % (err.size, precision, err.max(), p999, p99, err.mean()))
+    assert err.max() <= TOL[precision]
 
 
 def test_zero_frames_and_argument_errors(torch_mod, bfm):
