@@ -114,6 +114,27 @@ def cpu_baseline(raw, freqs, budget_s: float):
                       "%.3f channel-frames/s" % (done, len(all_units), dt, rate)}
 
 
+def copy_bandwidth(torch, mib: int = 1024, reps: int = 10) -> float:
+    """Measured HBM bandwidth of a plain device-to-device copy (bytes read + written
+    per second, GB/s): the attainable reference beside the datasheet 8 TB/s."""
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2 * n / s / 1e9
+
+
 def copy_probe(torch, mib: int, reps: int):
     """A plain device-to-device copy of known size, for counter calibration runs."""
     n = mib << 20
@@ -275,7 +296,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=25)
     ap.add_argument("--frames", type=int, default=128)
     ap.add_argument("--precision", default="all", choices=["fp32", "fp16", "fp32_mfma", "all"],
                     help="path(s) to time; with all, value is the FP32 FFT path's")
@@ -363,6 +384,13 @@ def main():
         del raw_all
     if args.copy_probe_mib:
         copy_probe(torch, args.copy_probe_mib, 3)
+    copy_gbs = copy_bandwidth(torch)
+    log("device copy: %.0f GB/s (read + write)" % copy_gbs)
+    for prec in paths:
+        for entry in [results[prec]] + [v for v in results[prec].values()
+                                        if isinstance(v, dict) and "hbm" in v]:
+            entry["hbm"]["copy_GBs"] = round(copy_gbs, 1)
+            entry["hbm"]["frac_of_copy"] = round(entry["hbm"]["achieved_GBs"] / copy_gbs, 4)
 
     if args.serve_frames > 0:
         for prec in paths:
