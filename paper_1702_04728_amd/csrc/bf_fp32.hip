@@ -27,7 +27,8 @@
 //      With the mirror-symmetric default geometry the pair shares its sums:
 //      S_c = y_c + y_(3-c), D_c = y_c - y_(3-c), beam jp = P + iQ and beam
 //      3 - jp = P - iQ with P = sum_c Re W[jp][c] S_c, Q = sum_c Im W[jp][c] D_c
-//      (c = 0, 1), 20 instead of 32 operations per feed and pair;
+//      (c = 0, 1), 20 instead of 32 operations per feed and pair; any other
+//      geometry (kSym false) forms both beams from the full four-cylinder sums;
 //   B2 each group transforms its two lines: 512 = 32 x 16 with the upper half
 //      of the input zero, so step 1 is a pruned 32-point DFT per lane (two
 //      16-point FFTs), then twiddles w512^(b c), a 16-lane transpose through LDS
