@@ -8,8 +8,8 @@ resident in HBM before timing), producing 1024 beams x 16 sub-channels per
 channel-frame.  Value = channel-frames per second x 0.98304 ms = frequency
 channels the GPU sustains in real time.
 
-Prints ONE JSON line (rank 0).  Multi-GPU runs are not part of this build:
---gpus above 1 exits with a message.
+Prints ONE JSON line (rank 0).  The library runs on one GPU (channels would
+shard across GPUs with no exchange): --gpus above 1 exits with a message.
 """
 from __future__ import annotations
 
@@ -323,8 +323,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(channels shard across GPUs with no exchange; see the design notes). "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(channels would shard across GPUs with no exchange). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

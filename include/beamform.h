@@ -55,7 +55,7 @@ extern "C" {
 #define BF_E_NOMEM (-2)       /* host or device allocation failed */
 #define BF_E_DEVICE (-3)      /* HIP runtime / kernel failure */
 #define BF_E_STATE (-4)       /* call not valid for the plan's state */
-#define BF_E_UNSUPPORTED (-5) /* valid request this build does not implement */
+#define BF_E_UNSUPPORTED (-5) /* valid request the library does not implement */
 
 typedef struct bf_plan bf_plan; /* opaque, library-owned */
 
