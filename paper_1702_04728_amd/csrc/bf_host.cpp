@@ -76,12 +76,14 @@ double default_cyl_x(int c) { return (c - 1.5) * 20.0; }
 double default_sin_theta(int m) { return (m - 127.5) / 128.0; }
 double default_sin_phi(int j) { return std::sin((j - 1.5) * 0.4 * kTwoPi / 360.0); }
 
-// Eq. (1) of the paper evaluated in FP64, then floor and reduction mod N P.
+// Eq. (1) of the paper evaluated in FP64, then floor and reduction mod N P;
+// -1 when the argument is too large for an exact integer floor.
 int32_t eq1_bin(const bf_config* c, double f_hz, double sin_theta)
 {
     const int nb = c->n_feed * c->pad;
     const double t = (double)c->n_feed * (double)c->pad * f_hz * (c->feed_spacing_m / c->c0) *
                      sin_theta + 0.5;
+    if (!(std::fabs(t) < 9.0e15)) return -1;  // beyond 2^53 floor is no longer exact
     long long k = (long long)std::floor(t);
     long long r = k % nb;
     if (r < 0) r += nb;
@@ -104,6 +106,7 @@ int32_t fill_lut(const bf_config* c, const double* freqs, int32_t n_chan, int32_
                 const double s = c->sin_theta_ns ? c->sin_theta_ns[m] : default_sin_theta(m);
                 if (!std::isfinite(s)) { *msg = "sin_theta_ns must be finite"; return BF_E_INVAL; }
                 k = eq1_bin(c, f, s);
+                if (k < 0) { *msg = "Eq. (1) argument out of range (frequency x sin_theta too large)"; return BF_E_INVAL; }
             }
             out[(size_t)ch * c->n_beam_ns + m] = k;
         }

@@ -73,6 +73,15 @@ def test_lut_custom_pointings_and_override(oracle_mod):
         bf.compute_lut(freqs, lut_override=ov)
 
 
+def test_lut_rejects_out_of_range_argument():
+    """A finite but huge frequency or pointing is refused instead of overflowing the
+    integer floor of Eq. (1)."""
+    with pytest.raises(bf.BeamformError):
+        bf.compute_lut([1e300])
+    with pytest.raises(bf.BeamformError):
+        bf.compute_lut([600e6], sin_theta_ns=np.full(256, 1e200))
+
+
 def test_lut_rejects_bad_frequency():
     with pytest.raises(bf.BeamformError):
         bf.compute_lut([600e6, -1.0])
