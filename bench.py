@@ -47,14 +47,14 @@ PEAK = {"fp32": (157.3, "TFLOP/s", "alu"),    # MI355X FP32 vector peak (publish
         "fp16": (2500.0, "TFLOP/s", "mfma"),  # MI355X dense FP16 matrix peak
         "fp32_mfma": (2500.0, "TFLOP/s", "mfma")}
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAME = {"fp32": "bf_fp32_kernel<true, false>", "fp16": "bf_mfma_kernel<true, false, false>",
-               "fp32_mfma": "bf_mfma_kernel<true, true, false>"}
+KERNEL_NAME = {"fp32": "bf_fp32_kernel<true, false>", "fp16": "bf_mfma_kernel<2, false, false>",
+               "fp32_mfma": "bf_mfma_kernel<2, true, false>"}
 # first pass of the 128-point up-channelisation
-FINE_KERNEL_NAME = {"fp32": "bf_fp32_kernel<true, true>", "fp16": "bf_mfma_kernel<true, false, true>",
-                    "fp32_mfma": "bf_mfma_kernel<true, true, true>"}
+FINE_KERNEL_NAME = {"fp32": "bf_fp32_kernel<true, true>", "fp16": "bf_mfma_kernel<2, false, true>",
+                    "fp32_mfma": "bf_mfma_kernel<2, true, true>"}
 # directions without mirror symmetry (tracking beams) take the general E-W form
-KERNEL_NAME_GENERAL = {"fp32": "bf_fp32_kernel<false, false>", "fp16": "bf_mfma_kernel<false, false, false>",
-                       "fp32_mfma": "bf_mfma_kernel<false, true, false>"}
+KERNEL_NAME_GENERAL = {"fp32": "bf_fp32_kernel<false, false>", "fp16": "bf_mfma_kernel<1, false, false>",
+                       "fp32_mfma": "bf_mfma_kernel<1, true, false>"}
 DTYPE = {"fp32": "f32", "fp16": "f16 x f16 -> f32 (MFMA)",
          "fp32_mfma": "f16 hi+lo pairs -> f32 (MFMA, FP32-class)"}
 PATH_NAME = {"fp32": "fp32_fft", "fp16": "fp16_mfma", "fp32_mfma": "fp32_mfma"}

@@ -133,6 +133,13 @@ bool mirror_symmetric(const double* cyl_x, const double* sin_phi)
     return cyl_x[3] == -cyl_x[0] && cyl_x[2] == -cyl_x[1] &&
            sin_phi[3] == -sin_phi[0] && sin_phi[2] == -sin_phi[1];
 }
+// Cylinder positions alone symmetric: W[j][3-c] = conj(W[j][c]) exactly for any
+// direction (the phase is negated exactly in FP64), which the matrix-core
+// kernels use for directions without mirror symmetry (tracking beams).
+bool cylinders_symmetric(const double* cyl_x)
+{
+    return cyl_x[3] == -cyl_x[0] && cyl_x[2] == -cyl_x[1];
+}
 
 // Checks shared by the batch entry points, then one launch over all units.
 int32_t launch_batch(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float* d_out,
@@ -154,6 +161,7 @@ int32_t launch_batch(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float* d
     a.st = nullptr;
     a.partial = nullptr;
     a.sym_ew = sym;
+    a.cyl_sym = p->cyl_sym;
     a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
     a.ew_by_unit = ew_by_unit;
     a.out_u8 = d_out_u8;
@@ -298,6 +306,7 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
     for (double v : p->sin_phi) if (!std::isfinite(v)) { delete p; return fail(nullptr, BF_E_INVAL, "sin_phi_ew must be finite"); }
 
     p->sym_ew = mirror_symmetric(p->cyl_x.data(), p->sin_phi.data()) ? 1 : 0;
+    p->cyl_sym = cylinders_symmetric(p->cyl_x.data()) ? 1 : 0;
 
     p->lut.resize((size_t)n_chan * bf::kBeamNS);
     bf_config tmp = *cfg;
@@ -427,6 +436,7 @@ int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_fram
         a.n_blk = n_it;
         a.n_time = p->cfg.n_time;
         a.sym_ew = p->sym_ew;
+        a.cyl_sym = p->cyl_sym;
         a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
         a.fine = p->d_fine;
         a.fine_stride8 = 1;
@@ -463,6 +473,7 @@ int32_t beamform_debug_ns(bf_plan* p, const uint8_t* d_in, float* d_ns_out, void
     a.n_blk = p->cfg.n_time / bf::kUp;
     a.n_time = p->cfg.n_time;
     a.sym_ew = p->sym_ew;
+    a.cyl_sym = p->cyl_sym;
     a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
     a.fine = reinterpret_cast<float2*>(d_ns_out);
     a.fine_stride8 = 0;

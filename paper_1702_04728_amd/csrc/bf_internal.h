@@ -61,6 +61,7 @@ struct LaunchArgs {
     int32_t n_time;        // stream mode: samples per frame (ring entry stride)
     int32_t max_slots;     // stream mode: slots per ring entry
     int32_t sym_ew;        // 1: x[3-c] = -x[c] and sin(phi[3-j]) = -sin(phi[j]) exactly
+    int32_t cyl_sym;       // 1: x[3-c] = -x[c] exactly (W[j][3-c] = conj W[j][c] for any phi)
     int32_t split_v;       // matrix-core path: 1 = E-W output also as hi + lo (FP32-class)
     int32_t ew_by_unit;    // 1: ew has one row per unit (batch mode)
     // 8-bit output (batch mode): out_u8[u][1024][16] = clamp(rint(P scale + offset))

@@ -92,26 +92,33 @@ __device__ __forceinline__ void split_half8(const float2 (&v)[4], half8& hi, hal
 }
 
 // E-W phasing of one (sub-channel, feed, pol) across the four cylinders:
-// b_j = sum_c W[j][c] y_c, written to v[j][ia] for j = 0..3.  With the mirror
-// symmetric geometry W[j][3-c] = W[3-j][c] = conj(W[j][c]), so with
-// S_c = y_c + y_(3-c), D_c = y_c - y_(3-c) (c = 0, 1):
-// b_j = P_j + i Q_j, b_(3-j) = P_j - i Q_j, P_j = sum Re W[j][c] S_c,
-// Q_j = sum Im W[j][c] D_c  (32 instead of 64 multiply-adds).
-template <bool kSym>
+// b_j = sum_c W[j][c] y_c, written to v[j][ia] for j = 0..3.  Forms (kEw):
+//   kEwMirror: cylinders and E-W directions both symmetric about the centre,
+//     W[j][3-c] = W[3-j][c] = conj(W[j][c]); with S_c = y_c + y_(3-c),
+//     D_c = y_c - y_(3-c) (c = 0, 1): b_j = P_j + i Q_j, b_(3-j) = P_j - i Q_j,
+//     P_j = sum Re W[j][c] S_c, Q_j = sum Im W[j][c] D_c (28 operations per
+//     feed instead of 56);
+//   kEwCyl: cylinders symmetric, directions arbitrary (tracking beams):
+//     W[j][3-c] = conj(W[j][c]) still, so b_j = P_j + i Q_j for every j from
+//     the shared S_c, D_c (48 operations);
+//   kEwGeneral: the plain four-cylinder sums (56 operations).
+constexpr int kEwGeneral = 0, kEwCyl = 1, kEwMirror = 2;
+template <int kEw>
 __device__ __forceinline__ void ew_phase(const float2 (&y)[4], const float2 (&W)[4][4],
                                          float2 (&v)[4][4], int ia)
 {
-    if constexpr (kSym) {
+    if constexpr (kEw != kEwGeneral) {
         const float2 S0 = cadd(y[0], y[3]), S1 = cadd(y[1], y[2]);
         const float2 D0 = csub(y[0], y[3]), D1 = csub(y[1], y[2]);
+        constexpr int kJ = kEw == kEwMirror ? 2 : 4;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < kJ; ++j) {
             const float2 P = make_float2(fmaf(W[j][0].x, S0.x, W[j][1].x * S1.x),
                                          fmaf(W[j][0].x, S0.y, W[j][1].x * S1.y));
             const float2 Q = make_float2(fmaf(W[j][0].y, D0.x, W[j][1].y * D1.x),
                                          fmaf(W[j][0].y, D0.y, W[j][1].y * D1.y));
             v[j][ia] = make_float2(P.x - Q.y, P.y + Q.x);
-            v[3 - j][ia] = make_float2(P.x + Q.y, P.y - Q.x);
+            if constexpr (kEw == kEwMirror) v[3 - j][ia] = make_float2(P.x + Q.y, P.y - Q.x);
         }
     } else {
 #pragma unroll
@@ -129,7 +136,7 @@ __device__ __forceinline__ void ew_phase(const float2 (&y)[4], const float2 (&W)
 // FP32-class (max relative power error ~1e-6 against FP64).
 // kFine: first pass of the 128-point up-channelisation (stride-8 sample
 // blocks; each line's kept beams written out instead of its power summed).
-template <bool kSym, bool kSplitV, bool kFine>
+template <int kEw, bool kSplitV, bool kFine>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bf_mfma_kernel(LaunchArgs a)
 {
@@ -195,7 +202,7 @@ void bf_mfma_kernel(LaunchArgs a)
         // E-W phasing straight into stage-1 A fragments: feeds 16 a + n, a = 4q + ia
         half8 A[4][2];
         [[maybe_unused]] half8 Alo[4][2];
-        if constexpr (kSym) {  // both pols per LDS read
+        if constexpr (kEw == kEwMirror) {  // both pols per LDS read
             float2 v[2][4][4];  // [p][j][ia]
 #pragma unroll
             for (int ia = 0; ia < 4; ++ia) {
@@ -206,8 +213,8 @@ void bf_mfma_kernel(LaunchArgs a)
                     y0[c] = make_float2(x4.x, x4.y);
                     y1[c] = make_float2(x4.z, x4.w);
                 }
-                ew_phase<kSym>(y0, W, v[0], ia);
-                ew_phase<kSym>(y1, W, v[1], ia);
+                ew_phase<kEw>(y0, W, v[0], ia);
+                ew_phase<kEw>(y1, W, v[1], ia);
             }
 #pragma unroll
             for (int p = 0; p < 2; ++p)
@@ -228,7 +235,7 @@ void bf_mfma_kernel(LaunchArgs a)
                         const float4 x4 = s_T[s2 * 1024 + tslot(c * 256 + 16 * (4 * q + ia) + n)];
                         y[c] = p ? make_float2(x4.z, x4.w) : make_float2(x4.x, x4.y);
                     }
-                    ew_phase<kSym>(y, W, v, ia);
+                    ew_phase<kEw>(y, W, v, ia);
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -318,21 +325,22 @@ hipError_t launch_mfma(const LaunchArgs& a, hipStream_t stream)
     if (a.n_units <= 0) return hipSuccess;
     LaunchArgs args = a;
     void* params[] = {&args};
-    const void* k;
-    if (a.fine) {
-        if (a.split_v)
-            k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true, true, true>)
-                         : reinterpret_cast<const void*>(&bf_mfma_kernel<false, true, true>);
-        else
-            k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true, false, true>)
-                         : reinterpret_cast<const void*>(&bf_mfma_kernel<false, false, true>);
-    } else if (a.split_v) {
-        k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true, true, false>)
-                     : reinterpret_cast<const void*>(&bf_mfma_kernel<false, true, false>);
-    } else {
-        k = a.sym_ew ? reinterpret_cast<const void*>(&bf_mfma_kernel<true, false, false>)
-                     : reinterpret_cast<const void*>(&bf_mfma_kernel<false, false, false>);
-    }
+    // [E-W form][split][fine]
+    static const void* const kKernels[3][2][2] = {
+        {{reinterpret_cast<const void*>(&bf_mfma_kernel<kEwGeneral, false, false>),
+          reinterpret_cast<const void*>(&bf_mfma_kernel<kEwGeneral, false, true>)},
+         {reinterpret_cast<const void*>(&bf_mfma_kernel<kEwGeneral, true, false>),
+          reinterpret_cast<const void*>(&bf_mfma_kernel<kEwGeneral, true, true>)}},
+        {{reinterpret_cast<const void*>(&bf_mfma_kernel<kEwCyl, false, false>),
+          reinterpret_cast<const void*>(&bf_mfma_kernel<kEwCyl, false, true>)},
+         {reinterpret_cast<const void*>(&bf_mfma_kernel<kEwCyl, true, false>),
+          reinterpret_cast<const void*>(&bf_mfma_kernel<kEwCyl, true, true>)}},
+        {{reinterpret_cast<const void*>(&bf_mfma_kernel<kEwMirror, false, false>),
+          reinterpret_cast<const void*>(&bf_mfma_kernel<kEwMirror, false, true>)},
+         {reinterpret_cast<const void*>(&bf_mfma_kernel<kEwMirror, true, false>),
+          reinterpret_cast<const void*>(&bf_mfma_kernel<kEwMirror, true, true>)}}};
+    const int ew = a.sym_ew ? kEwMirror : a.cyl_sym ? kEwCyl : kEwGeneral;
+    const void* k = kKernels[ew][a.split_v ? 1 : 0][a.fine ? 1 : 0];
     return hipLaunchKernel(k, dev::grid_for(a.n_units), dim3(dev::kThreads), params, 0, stream);
 }
 

@@ -19,6 +19,7 @@ struct bf_plan {
     float2* d_tw = nullptr;
     void* d_mf = nullptr;
     int32_t sym_ew = 0;              // geometry symmetric about the array centre
+    int32_t cyl_sym = 0;             // cylinder positions symmetric about the centre
     // Tracking E-W weights, double-buffered so that the host fills one table
     // while the previous call's kernel reads the other: device [cap][4][4],
     // pinned host staging of the same size, and the event recorded after the

@@ -302,6 +302,7 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     a.n_time = n_time;
     a.max_slots = S;
     a.sym_ew = p->sym_ew;
+    a.cyl_sym = p->cyl_sym;
     a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
     auto launch = [&](hipStream_t on) {
         return p->cfg.precision == BF_FP32_FFT ? bf::launch_fp32(a, on) : bf::launch_mfma(a, on);
