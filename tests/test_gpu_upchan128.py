@@ -66,13 +66,16 @@ def test_uniform_bytes_parity(torch_mod, bfm, oracle_mod, n_frames, n_chan, seed
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16", "fp32_mfma"])
-def test_general_geometry_parity(torch_mod, bfm, oracle_mod, precision):
-    """E-W directions without mirror symmetry take every kernel's general E-W form."""
+@pytest.mark.parametrize("cyl_x", [None, (-31.0, -9.5, 10.25, 29.0)])
+def test_general_geometry_parity(torch_mod, bfm, oracle_mod, precision, cyl_x):
+    """E-W directions without mirror symmetry, with the default (symmetric) cylinders
+    or asymmetric ones: the kernels' other E-W forms."""
     raw = synth.uniform_bytes(45, (1, 2, 384, 2048))
     freqs = synth.chan_freq_hz([300, 800])
     sphi = np.sin(np.deg2rad([-0.5, -0.1, 0.25, 0.7]))
-    got = _run(torch_mod, bfm, raw, freqs, 128, precision=precision, sin_phi_ew=sphi)
-    ref = oracle_mod.beamform_upchan128(oracle_mod.Geometry(sin_phi_ew=sphi), freqs, raw)
+    kw = {} if cyl_x is None else {"cyl_x_m": np.array(cyl_x)}
+    got = _run(torch_mod, bfm, raw, freqs, 128, precision=precision, sin_phi_ew=sphi, **kw)
+    ref = oracle_mod.beamform_upchan128(oracle_mod.Geometry(sin_phi_ew=sphi, **kw), freqs, raw)
     err = np.abs(got - ref) / ref
     assert err.max() <= TOLS[precision]
 
