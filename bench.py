@@ -30,10 +30,8 @@ METRIC = "frequency channels sustained in real time, FP32 vs FP16-MFMA; p99 fram
 FRAME_S = 384 * 2.56e-6                 # 0.98304 ms
 BYTES_PER_UNIT = 384 * 2048 + 1024 * 16 * 4  # 851,968 algorithmic HBM bytes per channel-frame
 # 128-point up-channelisation: kept beams of 24 sample phases x 16 sub-channels x
-# 8 lines x 256 N-S beams between the two passes, complex FP32 (8 B), or FP16
-# pairs (4 B) on the FP16 matrix-core path
-FINE_BEAMS_PER_UNIT = 24 * 16 * 8 * 256
-FINE_BYTES_PER_BEAM = {"fp32": 8, "fp16": 4, "fp32_mfma": 8}
+# 8 lines x 256 N-S beams, complex FP32, between the two passes
+FINE_BYTES_PER_UNIT = 24 * 16 * 8 * 256 * 8
 # Conventional flop count per sample (5 N log2 N FFTs): N-S 8 x 512-point = 184,320,
 # E-W 1024 beams x 2 pols x 4 complex MACs = 65,536, 2048 16-point DFTs = 40,960,
 # detection 8,192.  Times 384 samples per channel-frame.
@@ -186,7 +184,7 @@ def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None, u8=None, u
            " upchan128" if upchan == 128 else "", args.steps, ms_step))
     unit_bytes = BYTES_PER_UNIT - (3 * 65536 // 4 if u8 else 0)
     if upchan == 128:  # the first pass's beams, written once and read once
-        unit_bytes += 2 * FINE_BEAMS_PER_UNIT * FINE_BYTES_PER_BEAM[prec]
+        unit_bytes += 2 * FINE_BYTES_PER_UNIT
     kern_s = float(np.mean(per)) * 1e-3
     flops = FLOPS_PER_UNIT[prec] * units
     peak, punit, bound = PEAK[prec]

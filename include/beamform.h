@@ -130,12 +130,11 @@ int32_t beamform_frame(bf_plan *plan, const uint8_t *d_in, int32_t n_frames, flo
  * q = ((q' + 4) / 8) mod 16, the 8 fine channels nearest its centre.
  * Two passes: the beamforming kernel writes every kept beam of every (sample
  * phase, sub-channel) to a plan-owned workspace (6.3 MB per channel-frame of
- * FP32 pairs; 3.1 MB of FP16 pairs, scaled by 2^-8, for BF_FP16_MFMA;
- * allocated by the first call, so that call cannot be inside a graph capture;
- * about 256 channel-frames or one frame at a time), the second kernel
- * completes the 128-point transforms and integrates.
- * The plan's precision applies to the first pass (the spatial transforms)
- * and, for BF_FP16_MFMA, to the stored beams; the second pass is FP32.
+ * FP32 complex beams, allocated by the first call, so that call cannot be
+ * inside a graph capture; about 256 channel-frames or one frame at a time),
+ * the second kernel completes the 128-point transforms and integrates.
+ * The plan's precision applies to the first pass (the spatial transforms);
+ * the stored beams and the second pass are FP32.
  *   d_in, d_out: as beamform_frame (d_out fully overwritten).
  * Needs n_time % 128 == 0 (else BF_E_UNSUPPORTED); BF_E_NOMEM if the workspace
  * cannot be allocated. */

@@ -310,34 +310,18 @@ __device__ __forceinline__ void load_lut_lane(const int32_t* __restrict__ lut, i
 #pragma unroll
     for (int i = 0; i < N; ++i) lv[i] = lut[lane + (kBeamNS / N) * i];
 }
-// kHalfOk: the kernel may be asked for FP16 pairs (only the matrix-core
-// kernels are; the FP32 kernel always writes FP32 pairs).
-template <int N, bool kHalfOk>
+template <int N>
 __device__ __forceinline__ void write_fine_line(const float2* __restrict__ bins, const int32_t (&lv)[N],
-                                                const LaunchArgs& a, size_t idx, int lane)
+                                                float2* __restrict__ dst, int lane)
 {
-    if (kHalfOk && a.fine_half) {  // FP16 pairs of the beams scaled by kFineHalfScale
-        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-        uint32_t* dst = reinterpret_cast<uint32_t*>(a.fine) + idx;
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const float2 v = bins[lv[i]];
-            h2 h;
-            h[0] = (_Float16)(v.x * kFineHalfScale);
-            h[1] = (_Float16)(v.y * kFineHalfScale);
-            dst[lane + (kBeamNS / N) * i] = __builtin_bit_cast(uint32_t, h);
-        }
-    } else {
-        float2* dst = a.fine + idx;
-#pragma unroll
-        for (int i = 0; i < N; ++i) dst[lane + (kBeamNS / N) * i] = bins[lv[i]];
-    }
+    for (int i = 0; i < N; ++i) dst[lane + (kBeamNS / N) * i] = bins[lv[i]];
 }
-// First element of line (p * 4 + j), sub-channel k, block iteration it of a
-// unit in the complex-beam buffer (elements: FP32 or FP16 pairs).
-__device__ __forceinline__ size_t fine_line_index(const LaunchArgs& a, int unit, int it, int k, int line)
+// Line (p * 4 + j) of sub-channel k, block iteration it of a unit in the
+// complex-beam buffer.
+__device__ __forceinline__ float2* fine_line_ptr(const LaunchArgs& a, int unit, int it, int k, int line)
 {
-    return ((((size_t)unit * a.n_blk + it) * 16 + k) * 8 + line) * kBeamNS;
+    return a.fine + ((((size_t)unit * a.n_blk + it) * 16 + k) * 8 + line) * kBeamNS;
 }
 
 // End of frame: P[(s2 * 4 + j) * 512 + k] holds the integrated power of FFT

@@ -85,16 +85,15 @@ __device__ __forceinline__ void fft16(float2 (&v)[16])
 // Zero-padded 512-point N-S transform of one line held as x[a] = line[16 a + b]
 // by lane b of a 16-lane group; accumulates |X_k|^2 for k = 2 b + r + 32 d into
 // acc[r][d].  bufE / bufO: this group's two transpose buffers (adjacent).
-// kFine: instead, the kept beams of the line go to the complex-beam buffer at
-// element fine_idx (first pass of the 128-point up-channelisation), gathered
-// through the transpose buffers.
+// kFine: instead, the kept beams of the line go to fine_dst (first pass of the
+// 128-point up-channelisation), gathered through the transpose buffers.
 template <bool kFine>
 __device__ __forceinline__ void ns_line_power(const float2 (&x)[16], float (&acc)[2][16],
                                               float2* __restrict__ bufE,
                                               float2* __restrict__ bufO,
                                               const float4* __restrict__ tw, int b,
                                               const int32_t (&lv)[kFine ? 16 : 1],
-                                              const LaunchArgs& a, size_t fine_idx)
+                                              float2* __restrict__ fine_dst)
 {
     float2 E[16], O[16];
 #pragma unroll
@@ -156,7 +155,7 @@ __device__ __forceinline__ void ns_line_power(const float2 (&x)[16], float (&acc
             bins[2 * b + 1 + 32 * d] = O[d];
         }
         wave_lds_sync();
-        write_fine_line<16, false>(bins, lv, a, fine_idx, b);
+        write_fine_line<16>(bins, lv, fine_dst, b);
         wave_lds_sync();
     } else {
 #pragma unroll
@@ -257,11 +256,11 @@ void bf_fp32_kernel(LaunchArgs a)
         // first line).  The last block fetches itself again rather than
         // branch: one basic block schedules with fewer live registers.
         const int k = wk.s0 + 4 * s2;
-        ns_line_power<kFine>(v0, acc[0], bufE, bufO, s_tw, b, lv, a,
-                             fine_line_index(a, wk.unit, blk, k, pol * 4 + jl[0]));
+        ns_line_power<kFine>(v0, acc[0], bufE, bufO, s_tw, b, lv,
+                             kFine ? fine_line_ptr(a, wk.unit, blk, k, pol * 4 + jl[0]) : nullptr);
         load_block(block_base(src, min(blk + 1, a.n_blk - 1), s8), raw, t, block_stride(s8));
-        ns_line_power<kFine>(v1, acc[1], bufE, bufO, s_tw, b, lv, a,
-                             fine_line_index(a, wk.unit, blk, k, pol * 4 + jl[1]));
+        ns_line_power<kFine>(v1, acc[1], bufE, bufO, s_tw, b, lv,
+                             kFine ? fine_line_ptr(a, wk.unit, blk, k, pol * 4 + jl[1]) : nullptr);
         __syncthreads();
     }
     if constexpr (kFine) return;  // the second pass detects and integrates

@@ -408,9 +408,7 @@ int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_fram
     // whole frames per chunk (so a channel-frame's tables are its row mod
     // n_chan), about 256 channel-frames of first-pass output at a time
     const int32_t n_it = p->cfg.n_time / bf::kUp;
-    // the FP16 matrix-core path keeps its complex beams as FP16 pairs
-    const int32_t half = p->cfg.precision == BF_FP16_MFMA ? 1 : 0;
-    const size_t per_unit = (size_t)n_it * bf::kFinePerIter * (half ? 4 : 8);  // bytes
+    const size_t per_unit = (size_t)n_it * bf::kFinePerIter * sizeof(float2);  // bytes
     const int32_t frames_per_chunk = std::max<int32_t>(1, 256 / p->n_chan);
     const size_t chunk_units = (size_t)frames_per_chunk * p->n_chan;
     if (p->fine_cap_units < chunk_units) {
@@ -440,12 +438,10 @@ int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_fram
         a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
         a.fine = p->d_fine;
         a.fine_stride8 = 1;
-        a.fine_half = half;
         e = p->cfg.precision == BF_FP32_FFT ? bf::launch_fp32(a, s) : bf::launch_mfma(a, s);
         if (e != hipSuccess) return hip_fail(p, e, "first-pass launch");
         bf::UpchanArgs ua{};
         ua.fine = p->d_fine;
-        ua.fine_half = half;
         ua.tw128 = p->d_tw128;
         ua.out = d_out + u0 * bf::kOutPerUnit;
         ua.n_units = a.n_units;

@@ -77,15 +77,7 @@ struct LaunchArgs {
     // consecutive samples (the pre-detection beams).
     float2* fine;
     int32_t fine_stride8;
-    // 1: fine holds each beam as a pair of FP16 values scaled by kFineHalfScale
-    // (4 bytes per complex value; the FP16 matrix-core path)
-    int32_t fine_half;
 };
-// Exact power-of-two scale of FP16 complex beams: the largest beam a channel-
-// frame can produce (|x| <= 8 sqrt 2 per sample; x 16 samples x 4 cylinders x
-// 256 feeds < 2^18 in amplitude) stays below the FP16 maximum (65504), and
-// noise beams stay normal numbers.
-constexpr float kFineHalfScale = 1.0f / 256.0f;
 
 // Complex values per channel-frame in the first pass's output:
 // (n_time / 16 block iterations) x 16 sub-channels x 8 lines x 256 beams.
@@ -99,8 +91,7 @@ hipError_t launch_mfma(const LaunchArgs& a, hipStream_t stream);
 // out_u8 is set (scale/offset rows unit % n_chan).  tw128[u * 16 + k] =
 // w128^(u k) (FP64 rounded once).
 struct UpchanArgs {
-    const float2* fine;     // FP32 pairs, or FP16 pairs (scaled) when fine_half
-    int32_t fine_half;
+    const float2* fine;
     const float2* tw128;
     float* out;
     uint8_t* out_u8;

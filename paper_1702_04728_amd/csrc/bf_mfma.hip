@@ -293,8 +293,8 @@ void bf_mfma_kernel(LaunchArgs a)
                 }
                 if constexpr (kFine) {
                     wave_lds_sync();
-                    write_fine_line<4, true>(s_bins + s2 * 512, lv, a,
-                                       fine_line_index(a, wk.unit, blk, wk.s0 + 4 * s2, p * 4 + j), lane);
+                    write_fine_line<4>(s_bins + s2 * 512, lv,
+                                       fine_line_ptr(a, wk.unit, blk, wk.s0 + 4 * s2, p * 4 + j), lane);
                     wave_lds_sync();
                 }
             }

@@ -15,11 +15,9 @@
 // blocks into sub-channel q = ((q' + 4) / 8) mod 16 (the 8 fine channels
 // nearest its centre).
 //
-// One thread per (channel-frame, E-W beam j, N-S beams m .. m + NB - 1);
-// consecutive threads take consecutive m, so every load is 64 lanes x 8 B
-// contiguous (one FP32 complex beam, or two FP16 ones), and all of a thread's
-// fine bins and sub-channel sums stay in its registers.  FP16 beams carry the
-// exact scale kFineHalfScale, removed from the powers at the end.
+// One thread per (channel-frame, E-W beam j, N-S beam m); consecutive threads
+// take consecutive m, so every load is 64 lanes x 8 B contiguous, and all of a
+// thread's fine bins and sub-channel sums stay in its registers.
 #include <hip/hip_runtime.h>
 
 #include "bf_device.h"
@@ -45,98 +43,59 @@ __device__ __forceinline__ void dft8(float2 (&y)[8])
     }
 }
 
-// NB complex beams of one (line, iteration, sub-channel) row starting at beam
-// element e0: FP32 pairs (NB = 1) or FP16 pairs (NB = 2), 8 bytes per lane.
-template <bool kHalf>
-__device__ __forceinline__ void load_beams(const float2* __restrict__ fine, size_t e0,
-                                           float2 (&y)[kHalf ? 2 : 1])
-{
-    if constexpr (kHalf) {
-        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-        const h4 h = *reinterpret_cast<const h4*>(reinterpret_cast<const uint32_t*>(fine) + e0);
-        y[0] = make_float2((float)h[0], (float)h[1]);
-        y[1] = make_float2((float)h[2], (float)h[3]);
-    } else {
-        y[0] = fine[e0];
-    }
-}
-
-template <bool kHalf>
 __global__ __launch_bounds__(kUpThreads) void bf_upchan128_kernel(UpchanArgs a)
 {
-    constexpr int NB = kHalf ? 2 : 1;
-    constexpr int kPerUnit = kBeams / NB;
     const long long gid = (long long)blockIdx.x * kUpThreads + threadIdx.x;
-    const int unit = (int)(gid / kPerUnit);
+    const int unit = (int)(gid >> 10);
     if (unit >= a.n_units) return;
-    const int beam0 = (int)(gid % kPerUnit) * NB, j = beam0 >> 8, m0 = beam0 & 255;
+    const int beam = (int)(gid & 1023), j = beam >> 8, m = beam & 255;
 
-    float acc[NB][16];
+    float acc[16];
 #pragma unroll
-    for (int e = 0; e < NB; ++e)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[e][q] = 0.f;
-    const size_t base = (size_t)unit * a.n_blk128 * 8 * kFinePerIter;
+    for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+    const float2* base = a.fine + (size_t)unit * a.n_blk128 * 8 * kFinePerIter;
     for (int p = 0; p < 2; ++p) {
-        const size_t line = base + (size_t)(p * 4 + j) * kBeamNS + m0;
+        const float2* line = base + (size_t)(p * 4 + j) * kBeamNS + m;
         for (int b = 0; b < a.n_blk128; ++b) {
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
-                float2 y[NB][8];
+                float2 y[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    float2 v[NB];
-                    load_beams<kHalf>(a.fine, line + ((size_t)(b * 8 + u) * 16 + k) * 8 * kBeamNS, v);
+                for (int u = 0; u < 8; ++u)
+                    y[u] = line[((size_t)(b * 8 + u) * 16 + k) * 8 * kBeamNS];
 #pragma unroll
-                    for (int e = 0; e < NB; ++e) y[e][u] = v[e];
-                }
+                for (int u = 1; u < 8; ++u) y[u] = cmul(y[u], a.tw128[u * 16 + k]);
+                dft8(y);
+                // fine bin k + 16 r -> sub-channel ((k + 4) / 8 + 8 + 2 r) mod 16
 #pragma unroll
-                for (int e = 0; e < NB; ++e) {
-#pragma unroll
-                    for (int u = 1; u < 8; ++u) y[e][u] = cmul(y[e][u], a.tw128[u * 16 + k]);
-                    dft8(y[e]);
-                    // fine bin k + 16 r -> sub-channel ((k + 4) / 8 + 8 + 2 r) mod 16
-#pragma unroll
-                    for (int r = 0; r < 8; ++r) {
-                        const int q = ((k + 4) / 8 + 8 + 2 * r) & 15;
-                        acc[e][q] = fmaf(y[e][r].x, y[e][r].x, fmaf(y[e][r].y, y[e][r].y, acc[e][q]));
-                    }
+                for (int r = 0; r < 8; ++r) {
+                    const int q = ((k + 4) / 8 + 8 + 2 * r) & 15;
+                    acc[q] = fmaf(y[r].x, y[r].x, fmaf(y[r].y, y[r].y, acc[q]));
                 }
             }
         }
-    }
-    if constexpr (kHalf) {
-        constexpr float kUnscale = 1.0f / (kFineHalfScale * kFineHalfScale);  // exact
-#pragma unroll
-        for (int e = 0; e < NB; ++e)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) acc[e][q] *= kUnscale;
     }
 
+    const size_t o = ((size_t)unit * kBeams + beam) * kUp;
+    if (a.out_u8) {
+        const size_t row = (size_t)(unit % a.n_chan) * kOutPerUnit + (size_t)beam * kUp;
+        uint32_t w[4];
 #pragma unroll
-    for (int e = 0; e < NB; ++e) {
-        const int beam = beam0 + e;
-        const size_t o = ((size_t)unit * kBeams + beam) * kUp;
-        if (a.out_u8) {
-            const size_t row = (size_t)(unit % a.n_chan) * kOutPerUnit + (size_t)beam * kUp;
-            uint32_t w[4];
+        for (int i = 0; i < 4; ++i) {
+            w[i] = 0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                w[i] = 0;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int q = 4 * i + c;
-                    const float x = rintf(fmaf(acc[e][q], a.scale[row + q], a.offset[row + q]));
-                    w[i] |= (uint32_t)fminf(fmaxf(x, 0.f), 255.f) << (8 * c);
-                }
+            for (int c = 0; c < 4; ++c) {
+                const int q = 4 * i + c;
+                const float x = rintf(fmaf(acc[q], a.scale[row + q], a.offset[row + q]));
+                w[i] |= (uint32_t)fminf(fmaxf(x, 0.f), 255.f) << (8 * c);
             }
-            *reinterpret_cast<uint4*>(a.out_u8 + o) = make_uint4(w[0], w[1], w[2], w[3]);
-        } else {
-            float4* dst = reinterpret_cast<float4*>(a.out + o);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                dst[i] = make_float4(acc[e][4 * i], acc[e][4 * i + 1], acc[e][4 * i + 2], acc[e][4 * i + 3]);
         }
+        *reinterpret_cast<uint4*>(a.out_u8 + o) = make_uint4(w[0], w[1], w[2], w[3]);
+    } else {
+        float4* dst = reinterpret_cast<float4*>(a.out + o);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            dst[i] = make_float4(acc[4 * i], acc[4 * i + 1], acc[4 * i + 2], acc[4 * i + 3]);
     }
 }
 
@@ -147,11 +106,10 @@ hipError_t launch_upchan128(const UpchanArgs& a, hipStream_t stream)
     if (a.n_units <= 0) return hipSuccess;
     UpchanArgs args = a;
     void* params[] = {&args};
-    const long long threads = (long long)a.n_units * (a.fine_half ? kBeams / 2 : kBeams);
+    const long long threads = (long long)a.n_units * kBeams;
     const dim3 grid((unsigned)((threads + kUpThreads - 1) / kUpThreads));
-    const void* k = a.fine_half ? reinterpret_cast<const void*>(&bf_upchan128_kernel<true>)
-                                : reinterpret_cast<const void*>(&bf_upchan128_kernel<false>);
-    return hipLaunchKernel(k, grid, dim3(kUpThreads), params, 0, stream);
+    return hipLaunchKernel(reinterpret_cast<const void*>(&bf_upchan128_kernel), grid,
+                           dim3(kUpThreads), params, 0, stream);
 }
 
 }  // namespace bf
