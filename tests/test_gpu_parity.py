@@ -133,17 +133,21 @@ def test_coherent_rfi_parity(torch_mod, bfm, oracle_mod, precision):
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
-def test_config4_sky_parity(torch_mod, bfm, oracle_mod, precision):
+@pytest.mark.parametrize("sin_phi", [None, (-0.5, -0.1, 0.25, 0.7)])
+def test_config4_sky_parity(torch_mod, bfm, oracle_mod, precision, sin_phi):
     """Config-4 inputs (noise, dispersed DM-500 pulse, RFI tones in all inputs) for three
-    channels of the 64-channel sweep, over the frames where the pulse crosses them."""
+    channels of the 64-channel sweep, over the frames where the pulse crosses them; with
+    the default (mirror-symmetric) E-W beams and with directions that are not, which
+    take the kernels' other E-W form."""
     c_idx = synth.sweep_c_idx(64)[[20, 31, 50]]
     sky = synth.config4_sky(1004, c_idx)
     f = synth.chan_freq_hz(c_idx)
     arr = synth.dispersion_delay_s(f[1], 500) - synth.dispersion_delay_s(800e6, 500)
     f0 = int(arr / (384 * 2.56e-6))
     raw = synth.config4_frames(1004, c_idx, np.arange(f0 - 2, f0 + 2), sky=sky)
-    got = _run(torch_mod, bfm, raw, f, precision=precision)
-    ref = oracle_mod.beamform(oracle_mod.Geometry(), f, raw)
+    kw = {} if sin_phi is None else {"sin_phi_ew": np.sin(np.deg2rad(sin_phi))}
+    got = _run(torch_mod, bfm, raw, f, precision=precision, **kw)
+    ref = oracle_mod.beamform(oracle_mod.Geometry(**kw), f, raw)
     err = _rel(got, ref)
     print("config4 %s max rel err %.3e" % (precision, err.max()))
     assert err.max() <= TOL[precision]
