@@ -153,6 +153,25 @@ def test_config4_sky_parity(torch_mod, bfm, oracle_mod, precision, sin_phi):
     assert err.max() <= TOL[precision]
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_config4_all_64_channels(torch_mod, bfm, oracle_mod, precision):
+    """Config-4 inputs over every channel of the 64-channel sweep (400-800 MHz), two
+    frames, default and non-mirrored E-W directions: the per-output bound holds
+    across the band, RFI tones and pulse included."""
+    c_idx = synth.sweep_c_idx(64)
+    sky = synth.config4_sky(1004, c_idx)
+    f = synth.chan_freq_hz(c_idx)
+    arr = synth.dispersion_delay_s(f[31], 500) - synth.dispersion_delay_s(800e6, 500)
+    f0 = int(arr / (384 * 2.56e-6))
+    raw = synth.config4_frames(1004, c_idx, np.arange(f0, f0 + 2), sky=sky)
+    for kw in ({}, {"sin_phi_ew": np.sin(np.deg2rad([-0.5, -0.1, 0.25, 0.7]))}):
+        got = _run(torch_mod, bfm, raw, f, precision=precision, **kw)
+        ref = oracle_mod.beamform(oracle_mod.Geometry(**kw), f, raw)
+        err = _rel(got, ref)
+        print("config4 64 channels %s %s max rel err %.3e" % (precision, "mirror" if not kw else "non-mirrored", err.max()))
+        assert err.max() <= TOL[precision]
+
+
 def test_energy_even_odd_bins_on_gpu(torch_mod, bfm, oracle_mod):
     """Parseval through the whole path on the GPU: even-bin run + odd-bin run with
     the scaled-unitary E-W directions sums to 16 * 4 * 512 * sum|x|^2."""
