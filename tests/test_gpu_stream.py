@@ -84,6 +84,36 @@ def test_stream_outputs_match_batch_and_oracle(torch_mod, bfm, oracle_mod, pool,
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16", "fp32_mfma"])
+def test_stream_full_size_512_channels(torch_mod, bfm, oracle_mod, precision):
+    """The max-load sweep's launch configuration at full size: 512 channels over
+    400-800 MHz, all joined at frame 0, hipGraph replay, whole frames, config-4 frames
+    tiled over a 2-deep ring.  Every output of the last two frames equals the batch
+    path on the same bytes (bit for bit), and sampled channel-frames match the oracle."""
+    n = 512
+    c_idx = synth.sweep_c_idx(n)
+    freqs = synth.chan_freq_hz(c_idx)
+    pool16 = torch_mod.from_numpy(
+        synth.config4_frames(1004, synth.sweep_c_idx(16), [0]).reshape(16, 384, 2048)).cuda()
+    depth = 2
+    idx = torch_mod.tensor([(7 * k + s) % 16 for k in range(depth) for s in range(n)], device="cuda")
+    ring = pool16[idx].reshape(depth, n, 384, 2048).contiguous()
+    events = [(0, J, int(c), float(f)) for c, f in zip(c_idx, freqs)]
+    st, log, out = _stream(torch_mod, bfm, ring, precision, n_frames=4, events=events,
+                           use_graph=True)
+    assert st["frames"] == 4 and st["channel_frames"] == 4 * n
+    assert (log[-1] == c_idx).all()
+    with bfm.Beamformer(freqs, precision=precision) as b:
+        for i in (2, 3):
+            ref = b.frame(ring[i % depth][None]).cpu().numpy()[0]
+            np.testing.assert_array_equal(out[i % depth], ref)
+    for s_ in (0, 170, 341, 511):
+        raw = ring[3 % depth, s_].cpu().numpy()[None, None]
+        o = oracle_mod.beamform(oracle_mod.Geometry(), [freqs[s_]], raw)[0, 0]
+        assert np.max(np.abs(out[3 % depth, s_] - o) / o) <= TOL[precision], s_
+    del ring, pool16
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp32_mfma"])
 @pytest.mark.parametrize("chunk", [128, 16])
 def test_chunked_partial_sums_equal_whole_frames(torch_mod, bfm, pool, precision, chunk):
     ring = _ring(torch_mod, pool, 3, 5)
