@@ -229,7 +229,8 @@ typedef struct {
                                  would exceed it, or find no free slot, is rejected */
     const bf_stream_event *events; /* host, sorted by frame; may be NULL if n_events = 0 */
     int32_t n_events;
-    int32_t reserved;              /* must be 0 */
+    int32_t warmup_frames;         /* frames at the start left out of the latency, late-frame
+                                      and service statistics (0 .. n_frames) */
     int32_t *slot_log;        /* optional host int32 [n_frames][max_slots]: channel id held
                                  by each slot during each frame, -1 when empty */
 } bf_stream_desc;
@@ -238,7 +239,9 @@ typedef struct {
     int64_t frames;           /* frames run */
     int64_t launches;         /* kernel launches (frames x chunks) */
     int64_t channel_frames;   /* sum over frames of active channels */
-    int64_t late_frames;      /* frames whose latency exceeded n_time x 2.56 us */
+    int64_t late_frames;      /* frames whose latency exceeded n_time x 2.56 us (latency,
+                                 late-frame and service figures cover the frames after
+                                 desc->warmup_frames; the counts cover every frame) */
     int64_t joins, leaves, rejected_joins, ignored_events;
     int32_t max_active, min_active;
     double latency_p50_ms, latency_p99_ms, latency_max_ms, latency_mean_ms;

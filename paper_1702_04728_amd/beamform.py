@@ -73,7 +73,7 @@ class BfStreamDesc(ctypes.Structure):
                 ("pacing", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("mem_cap_bytes", ctypes.c_int64),
                 ("events", ctypes.POINTER(BfStreamEvent)), ("n_events", ctypes.c_int32),
-                ("reserved", ctypes.c_int32),
+                ("warmup_frames", ctypes.c_int32),
                 ("slot_log", ctypes.POINTER(ctypes.c_int32))]
 
 
@@ -104,7 +104,7 @@ def _events_array(events):
 
 
 def _stream_desc(depth, max_slots, n_frames, chunk, pacing, use_graph, mem_cap_bytes, events,
-                 slot_log, d_in=None, d_out=None):
+                 slot_log, d_in=None, d_out=None, warmup_frames=0):
     arr, n_ev = _events_array(events)
     d = BfStreamDesc()
     d.d_in_ring = d_in
@@ -113,7 +113,7 @@ def _stream_desc(depth, max_slots, n_frames, chunk, pacing, use_graph, mem_cap_b
     d.pacing, d.use_graph, d.mem_cap_bytes = int(pacing), int(use_graph), int(mem_cap_bytes)
     d.events = arr
     d.n_events = n_ev
-    d.reserved = 0
+    d.warmup_frames = int(warmup_frames)
     if slot_log is not None:
         d.slot_log = slot_log.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     return d, arr
@@ -368,10 +368,11 @@ class Beamformer:
         return out
 
     def stream(self, in_ring, out_ring, events, n_frames, chunk=0, pacing=False, use_graph=True,
-               mem_cap_bytes=0, stream=None, log_slots=True):
+               mem_cap_bytes=0, stream=None, log_slots=True, warmup_frames=0):
         """Run the serving loop (blocking).  in_ring: CUDA uint8 [depth][max_slots][n_time][2048];
         out_ring: CUDA float32 [depth][max_slots][1024][16]; events: (frame, op, channel_id,
-        freq_hz) tuples sorted by frame.  Returns (stats dict, slot_log [n_frames][max_slots])."""
+        freq_hz) tuples sorted by frame; latency and service statistics leave out the first
+        warmup_frames frames.  Returns (stats dict, slot_log [n_frames][max_slots])."""
         import torch
         if not (isinstance(in_ring, torch.Tensor) and in_ring.is_cuda and in_ring.dtype == torch.uint8
                 and in_ring.is_contiguous() and in_ring.dim() == 4
@@ -387,7 +388,7 @@ class Beamformer:
         log = np.full((n_frames, max_slots), -1, dtype=np.int32) if log_slots else None
         d, keep = _stream_desc(depth, max_slots, n_frames, chunk, pacing, use_graph,
                                mem_cap_bytes, events, log, ctypes.c_void_p(in_ring.data_ptr()),
-                               ctypes.c_void_p(out_ring.data_ptr()))
+                               ctypes.c_void_p(out_ring.data_ptr()), warmup_frames)
         st = BfStreamStats()
         rc = self.lib.beamform_stream(self._plan, ctypes.byref(d), ctypes.byref(st),
                                       _stream_handle(stream))

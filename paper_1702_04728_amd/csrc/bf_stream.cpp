@@ -105,7 +105,10 @@ int32_t check_desc(const bf_stream_desc* d, std::string* msg)
     }
     if (d->n_frames < 0) { *msg = "n_frames < 0"; return BF_E_INVAL; }
     if (d->n_events < 0 || (d->n_events > 0 && !d->events)) { *msg = "bad events"; return BF_E_INVAL; }
-    if (d->reserved != 0) { *msg = "reserved must be 0"; return BF_E_INVAL; }
+    if (d->warmup_frames < 0 || d->warmup_frames > d->n_frames) {
+        *msg = "warmup_frames must be in [0, n_frames]";
+        return BF_E_INVAL;
+    }
     if (d->pacing != 0 && d->pacing != 1) { *msg = "pacing must be 0 or 1"; return BF_E_INVAL; }
     if (d->mem_cap_bytes < 0) { *msg = "mem_cap_bytes < 0"; return BF_E_INVAL; }
     for (int32_t i = 1; i < d->n_events; ++i)
@@ -449,6 +452,9 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     st->leaves = sch.leaves;
     st->rejected_joins = sch.rejected;
     st->ignored_events = sch.ignored + (d->n_events - evi);
+    // latency and service statistics over the frames after the warm-up
+    lat_ms.erase(lat_ms.begin(), lat_ms.begin() + d->warmup_frames);
+    svc_ms.erase(svc_ms.begin(), svc_ms.begin() + d->warmup_frames);
     for (double v : lat_ms) if (v > budget_ms) ++st->late_frames;
     st->latency_p50_ms = quantile(lat_ms, 0.50);
     st->latency_p99_ms = quantile(lat_ms, 0.99);

@@ -170,5 +170,13 @@ def test_stream_argument_errors(torch_mod, bfm, pool):
             b.stream(ring, out, [(2, J, 1, 5e8), (1, J, 2, 5e8)], 3)
         with pytest.raises(ValueError):
             b.stream(ring, out[:1], [], 3)
+        with pytest.raises(bfm.BeamformError):
+            b.stream(ring, out, [], 3, warmup_frames=4)
+        with pytest.raises(bfm.BeamformError):
+            b.stream(ring, out, [], 3, warmup_frames=-1)
         st, _ = b.stream(ring, out, [], 0)
         assert st["frames"] == 0
+        # statistics after a warm-up: every frame still runs, the figures cover the rest
+        st, _ = b.stream(ring, out, [(0, J, 1, 5e8)], 5, warmup_frames=5)
+        assert st["frames"] == 5 and st["channel_frames"] == 5 and st["late_frames"] == 0
+        assert st["latency_p99_ms"] == 0.0
