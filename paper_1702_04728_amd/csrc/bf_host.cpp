@@ -445,7 +445,6 @@ int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_fram
         ua.tw128 = p->d_tw128;
         ua.out = d_out + u0 * bf::kOutPerUnit;
         ua.n_units = a.n_units;
-        ua.n_chan = p->n_chan;
         ua.n_blk128 = p->cfg.n_time / 128;
         if ((e = bf::launch_upchan128(ua, s)) != hipSuccess) return hip_fail(p, e, "second-pass launch");
     }

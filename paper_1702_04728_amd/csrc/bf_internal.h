@@ -87,18 +87,13 @@ hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream);
 hipError_t launch_mfma(const LaunchArgs& a, hipStream_t stream);
 
 // Second pass of the 128-point up-channelisation: fine[unit][24][16][8][256]
-// (first-pass output) -> out[unit][1024][16] Stokes I, or 8-bit codes when
-// out_u8 is set (scale/offset rows unit % n_chan).  tw128[u * 16 + k] =
+// (first-pass output) -> out[unit][1024][16] Stokes I.  tw128[u * 16 + k] =
 // w128^(u k) (FP64 rounded once).
 struct UpchanArgs {
     const float2* fine;
     const float2* tw128;
     float* out;
-    uint8_t* out_u8;
-    const float* scale;
-    const float* offset;
     int32_t n_units;
-    int32_t n_chan;
     int32_t n_blk128;   // 128-sample blocks per frame
 };
 hipError_t launch_upchan128(const UpchanArgs& a, hipStream_t stream);

@@ -76,27 +76,10 @@ __global__ __launch_bounds__(kUpThreads) void bf_upchan128_kernel(UpchanArgs a)
         }
     }
 
-    const size_t o = ((size_t)unit * kBeams + beam) * kUp;
-    if (a.out_u8) {
-        const size_t row = (size_t)(unit % a.n_chan) * kOutPerUnit + (size_t)beam * kUp;
-        uint32_t w[4];
+    float4* dst = reinterpret_cast<float4*>(a.out + ((size_t)unit * kBeams + beam) * kUp);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            w[i] = 0;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int q = 4 * i + c;
-                const float x = rintf(fmaf(acc[q], a.scale[row + q], a.offset[row + q]));
-                w[i] |= (uint32_t)fminf(fmaxf(x, 0.f), 255.f) << (8 * c);
-            }
-        }
-        *reinterpret_cast<uint4*>(a.out_u8 + o) = make_uint4(w[0], w[1], w[2], w[3]);
-    } else {
-        float4* dst = reinterpret_cast<float4*>(a.out + o);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            dst[i] = make_float4(acc[4 * i], acc[4 * i + 1], acc[4 * i + 2], acc[4 * i + 3]);
-    }
+    for (int i = 0; i < 4; ++i)
+        dst[i] = make_float4(acc[4 * i], acc[4 * i + 1], acc[4 * i + 2], acc[4 * i + 3]);
 }
 
 }  // namespace
