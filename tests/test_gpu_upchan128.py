@@ -96,6 +96,24 @@ def test_many_chunks_sampled(torch_mod, bfm, oracle_mod):
         assert err.max() <= TOL, (f, c, err.max())
 
 
+def test_uneven_chunks_match_one_chunk(torch_mod, bfm, oracle_mod):
+    """4 channels x 66 frames: workspace chunks of 64 and 2 frames, the second
+    reusing the first's workspace.  Frames 62-65 (both sides of the chunk boundary)
+    equal, bit for bit, the same frames beamformed in one call of their own (one
+    chunk), and two of them match the oracle."""
+    n_frames, n_chan = 66, 4
+    raw = synth.uniform_bytes(46, (n_frames, n_chan, 384, 2048))
+    freqs = synth.chan_freq_hz([100, 400, 700, 1000])
+    whole = _run(torch_mod, bfm, raw, freqs, 128)
+    part = _run(torch_mod, bfm, raw[62:], freqs, 128)
+    assert np.array_equal(whole[62:], part)
+    units = [(63, 1), (65, 2)]
+    ref = oracle_mod.beamform_upchan128(oracle_mod.Geometry(), freqs, raw, units=units)
+    for i, (f, c) in enumerate(units):
+        err = np.abs(whole[f, c] - ref[i]) / ref[i]
+        assert err.max() <= TOL, (f, c, err.max())
+
+
 def test_closed_form_relations_to_16_point(torch_mod, bfm):
     """Channel-centre tone (exact integer samples): sub-channel 8 only, 8 times the
     16-point power (3 x 128^2 against 24 x 16^2); uniform bytes: total power 8 times
