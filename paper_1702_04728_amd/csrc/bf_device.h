@@ -76,6 +76,27 @@ __device__ __forceinline__ float2 tw32(float2 a)
 template <int K>
 __device__ __forceinline__ float2 tw16(float2 a) { return tw32<2 * K>(a); }
 
+// w32^K (a - o (1 + i)): the offset o rides in the addend of the twiddle's
+// fused multiply-adds, so a non-trivial twiddle costs no more than without it
+// (re = a.x c + a.y s - o (c + s), im = a.y c - a.x s - o (c - s) for
+// w32^K = c - i s).
+template <int K>
+__device__ __forceinline__ float2 tw32_off(float2 a, float o)
+{
+    constexpr int k = ((K % 32) + 32) % 32;
+    if constexpr (k % 8 == 0) {
+        return rot<k / 8>(make_float2(a.x - o, a.y - o));
+    } else if constexpr (k < 8) {
+        const float2 cs = cs32<k>();
+        return make_float2(fmaf(a.x, cs.x, fmaf(a.y, cs.y, -o * (cs.x + cs.y))),
+                           fmaf(a.y, cs.x, fmaf(-a.x, cs.y, -o * (cs.x - cs.y))));
+    } else {
+        return rot<k / 8>(tw32_off<k % 8>(a, o));
+    }
+}
+template <int K>
+__device__ __forceinline__ float2 tw16_off(float2 a, float o) { return tw32_off<2 * K>(a, o); }
+
 // In-place DFT-4: X_k = sum_n x_n (-i)^(n k).
 __device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d)
 {
@@ -181,6 +202,15 @@ __device__ __forceinline__ void store_partial(const float* acc, float* __restric
     for (int e = 0; e < N; ++e) p[e * kThreads + t] = acc[e];
 }
 
+// a + b + c in one instruction.  Written in C++, a + b + bias with a bias
+// whose bits the nibbles cannot reach becomes an OR and two adds.
+__device__ __forceinline__ uint32_t add3_u32(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
 // LDS position (in float4) of time-DFT slot sigma = cyl * 256 + feed: bits 4-5
 // are XORed into bits 0-1.  The time DFT writes slots 4 t + h (lane stride 4)
 // and E-W phasing reads 16 consecutive slots; with the swizzle both touch 16
@@ -219,14 +249,14 @@ __device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restr
                 yr[t1][w] = r[0] + r[1] + r[2] + r[3];  // = sum(value) + 32
                 yi[t1][w] = m[0] + m[1] + m[2] + m[3];
             } else if constexpr (S0 == 1) {  // x0 - i x1 - x2 + i x3
-                yr[t1][w] = (r[0] + m[1] + kBias) - (r[2] + m[3]);
-                yi[t1][w] = (m[0] + r[3] + kBias) - (r[1] + m[2]);
+                yr[t1][w] = add3_u32(r[0], m[1], kBias) - (r[2] + m[3]);
+                yi[t1][w] = add3_u32(m[0], r[3], kBias) - (r[1] + m[2]);
             } else if constexpr (S0 == 2) {  // x0 - x1 + x2 - x3
-                yr[t1][w] = (r[0] + r[2] + kBias) - (r[1] + r[3]);
-                yi[t1][w] = (m[0] + m[2] + kBias) - (m[1] + m[3]);
+                yr[t1][w] = add3_u32(r[0], r[2], kBias) - (r[1] + r[3]);
+                yi[t1][w] = add3_u32(m[0], m[2], kBias) - (m[1] + m[3]);
             } else {  // x0 + i x1 - x2 - i x3
-                yr[t1][w] = (r[0] + m[3] + kBias) - (m[1] + r[2]);
-                yi[t1][w] = (m[0] + r[1] + kBias) - (m[2] + r[3]);
+                yr[t1][w] = add3_u32(r[0], m[3], kBias) - (m[1] + r[2]);
+                yi[t1][w] = add3_u32(m[0], r[1], kBias) - (m[2] + r[3]);
             }
         }
     }
@@ -237,16 +267,18 @@ __device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restr
         for (int p = 0; p < 2; ++p) {
             const int e = 2 * h + p;  // input 8t + e: feed 4 (t % 64) + h, pol p
             const int w = e >> 2;
-            // each byte is value + 32 (both components)
-            constexpr float kOff = S0 == 0 ? 0.f : 32.f;
+            // each byte is value + 32 (both components); the offset is taken
+            // off inside the twiddles (class 0: at bin 0 after the transform)
             float2 y[4];
 #pragma unroll
             for (int t1 = 0; t1 < 4; ++t1)
-                y[t1] = make_float2(ubyte_to_float(yr[t1][w], e & 3) - kOff,
-                                    ubyte_to_float(yi[t1][w], e & 3) - kOff);
-            y[1] = tw16<S0>(y[1]);
-            y[2] = tw16<2 * S0>(y[2]);
-            y[3] = tw16<3 * S0>(y[3]);
+                y[t1] = make_float2(ubyte_to_float(yr[t1][w], e & 3), ubyte_to_float(yi[t1][w], e & 3));
+            if constexpr (S0 != 0) {
+                y[0] = make_float2(y[0].x - 32.f, y[0].y - 32.f);
+                y[1] = tw16_off<S0>(y[1], 32.f);
+                y[2] = tw16_off<2 * S0>(y[2], 32.f);
+                y[3] = tw16_off<3 * S0>(y[3], 32.f);
+            }
             dft4(y[0], y[1], y[2], y[3]);
             if constexpr (S0 == 0) {
                 // no twiddles: the offset reaches only bin 0, as 4 x 32, and every
