@@ -76,27 +76,6 @@ __device__ __forceinline__ float2 tw32(float2 a)
 template <int K>
 __device__ __forceinline__ float2 tw16(float2 a) { return tw32<2 * K>(a); }
 
-// w32^K (a - o (1 + i)): the offset o rides in the addend of the twiddle's
-// fused multiply-adds, so a non-trivial twiddle costs no more than without it
-// (re = a.x c + a.y s - o (c + s), im = a.y c - a.x s - o (c - s) for
-// w32^K = c - i s).
-template <int K>
-__device__ __forceinline__ float2 tw32_off(float2 a, float o)
-{
-    constexpr int k = ((K % 32) + 32) % 32;
-    if constexpr (k % 8 == 0) {
-        return rot<k / 8>(make_float2(a.x - o, a.y - o));
-    } else if constexpr (k < 8) {
-        const float2 cs = cs32<k>();
-        return make_float2(fmaf(a.x, cs.x, fmaf(a.y, cs.y, -o * (cs.x + cs.y))),
-                           fmaf(a.y, cs.x, fmaf(-a.x, cs.y, -o * (cs.x - cs.y))));
-    } else {
-        return rot<k / 8>(tw32_off<k % 8>(a, o));
-    }
-}
-template <int K>
-__device__ __forceinline__ float2 tw16_off(float2 a, float o) { return tw32_off<2 * K>(a, o); }
-
 // In-place DFT-4: X_k = sum_n x_n (-i)^(n k).
 __device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d)
 {
@@ -267,18 +246,18 @@ __device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restr
         for (int p = 0; p < 2; ++p) {
             const int e = 2 * h + p;  // input 8t + e: feed 4 (t % 64) + h, pol p
             const int w = e >> 2;
-            // each byte is value + 32 (both components); the offset is taken
-            // off inside the twiddles (class 0: at bin 0 after the transform)
+            // each byte is value + 32 (both components); the exact subtraction
+            // keeps a zero-valued input exactly zero (class 0: the offset reaches
+            // only bin 0 and is removed there)
+            constexpr float kOff = S0 == 0 ? 0.f : 32.f;
             float2 y[4];
 #pragma unroll
             for (int t1 = 0; t1 < 4; ++t1)
-                y[t1] = make_float2(ubyte_to_float(yr[t1][w], e & 3), ubyte_to_float(yi[t1][w], e & 3));
-            if constexpr (S0 != 0) {
-                y[0] = make_float2(y[0].x - 32.f, y[0].y - 32.f);
-                y[1] = tw16_off<S0>(y[1], 32.f);
-                y[2] = tw16_off<2 * S0>(y[2], 32.f);
-                y[3] = tw16_off<3 * S0>(y[3], 32.f);
-            }
+                y[t1] = make_float2(ubyte_to_float(yr[t1][w], e & 3) - kOff,
+                                    ubyte_to_float(yi[t1][w], e & 3) - kOff);
+            y[1] = tw16<S0>(y[1]);
+            y[2] = tw16<2 * S0>(y[2]);
+            y[3] = tw16<3 * S0>(y[3]);
             dft4(y[0], y[1], y[2], y[3]);
             if constexpr (S0 == 0) {
                 // no twiddles: the offset reaches only bin 0, as 4 x 32, and every
