@@ -58,39 +58,51 @@ __device__ __forceinline__ half8 pack_half8(const float2 (&v)[4])
     return h;
 }
 
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// Low halves of the hi/lo split of (x0, x1), hpair = fp16(x0) | fp16(x1) << 16:
-// fp16(x - hi) computed by the mixed-precision FMA (x - hi is exact in FP32),
-// two instructions for two values.
-__device__ __forceinline__ uint32_t split_lo_pair(uint32_t hpair, float x0, float x1)
-{
-    uint32_t r;
-    asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]\n\t"
-        "v_fma_mixhi_f16 %0, %1, -1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
-        : "=&v"(r)
-        : "v"(hpair), "v"(x0), "v"(x1));
-    return r;
-}
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 
 // hi = fp16(v), lo = fp16(v - hi): together they carry ~22 significant bits.
+// hi is the compiler's own packed round-to-nearest conversion.  The empty asm
+// makes each value opaque first, so that the compiler cannot fold the
+// conversion into the FMA that produced the value (a mixed-precision FMA with
+// an FP16 result, which would also keep that FMA in FP32 for the lo half: two
+// instructions per value instead of one per pair, 6-10 % of the kernel's
+// time); it emits no instruction.  lo is one mixed-precision FMA per value,
+// x - hi, which is exact in FP32 (the compiler does not form it itself, so it
+// is written out).  Both halves feed matrix-core instructions, and the
+// hardware needs two wait states between a VALU write of a register and an
+// MFMA read of it; the compiler inserts them only after instructions it can
+// see, so the block of lo instructions ends with its own s_nop.
 __device__ __forceinline__ void split_half8(const float2 (&v)[4], half8& hi, half8& lo)
 {
-    u32x4 h, l;
+    float x[8];
+    uint32_t h[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        // hi: one packed round-to-nearest conversion of both values.  Written as
-        // two scalar casts, the compiler folds each into the FMA that produced
-        // its value (a mixed-precision FMA with an FP16 result) and keeps that
-        // FMA in FP32 as well for the low half: two instructions per value
-        // instead of one per pair, and 6-10 % of the kernel's time.
-        uint32_t hb;
-        asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(hb) : "v"(v[i].x), "v"(v[i].y));
-        h[i] = hb;
-        l[i] = split_lo_pair(hb, v[i].x, v[i].y);
+        x[2 * i] = v[i].x;
+        x[2 * i + 1] = v[i].y;
+        asm volatile("" : "+v"(x[2 * i]), "+v"(x[2 * i + 1]));
+        half2v hp;
+        hp[0] = (_Float16)x[2 * i];
+        hp[1] = (_Float16)x[2 * i + 1];
+        h[i] = __builtin_bit_cast(uint32_t, hp);
     }
-    hi = __builtin_bit_cast(half8, h);
-    lo = __builtin_bit_cast(half8, l);
+    uint32_t l[4];
+    asm("v_fma_mixlo_f16 %0, %4, -1.0, %8 op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixhi_f16 %0, %4, -1.0, %9 op_sel:[1,0,0] op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixlo_f16 %1, %5, -1.0, %10 op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixhi_f16 %1, %5, -1.0, %11 op_sel:[1,0,0] op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixlo_f16 %2, %6, -1.0, %12 op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixhi_f16 %2, %6, -1.0, %13 op_sel:[1,0,0] op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixlo_f16 %3, %7, -1.0, %14 op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixhi_f16 %3, %7, -1.0, %15 op_sel:[1,0,0] op_sel_hi:[1,0,0]\n\t"
+        "s_nop 1"
+        : "=&v"(l[0]), "=&v"(l[1]), "=&v"(l[2]), "=&v"(l[3])
+        : "v"(h[0]), "v"(h[1]), "v"(h[2]), "v"(h[3]),
+          "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(x[3]), "v"(x[4]), "v"(x[5]), "v"(x[6]), "v"(x[7]));
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 hv = {h[0], h[1], h[2], h[3]}, lv = {l[0], l[1], l[2], l[3]};
+    hi = __builtin_bit_cast(half8, hv);
+    lo = __builtin_bit_cast(half8, lv);
 }
 
 // E-W phasing of one (sub-channel, feed, pol) across the four cylinders:
