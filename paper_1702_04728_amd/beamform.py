@@ -119,11 +119,13 @@ def _stream_desc(depth, max_slots, n_frames, chunk, pacing, use_graph, mem_cap_b
     return d, arr
 
 
-def stream_schedule(events, n_frames, max_slots, per_slot_bytes, cap_bytes, depth=1):
+def stream_schedule(events, n_frames, max_slots, per_slot_bytes, cap_bytes, depth=1,
+                    warmup_frames=0):
     """Host-only dry run of the serving loop's scheduler: (stats dict, slot_log)."""
     lib = load_library()
     log = np.full((n_frames, max_slots), -1, dtype=np.int32)
-    d, keep = _stream_desc(depth, max_slots, n_frames, 0, 0, 0, 0, events, log)
+    d, keep = _stream_desc(depth, max_slots, n_frames, 0, 0, 0, 0, events, log,
+                           warmup_frames=warmup_frames)
     st = BfStreamStats()
     _check(lib.beamform_stream_schedule(ctypes.byref(d), int(per_slot_bytes), int(cap_bytes),
                                         ctypes.byref(st)))

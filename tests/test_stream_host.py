@@ -119,3 +119,9 @@ def test_schedule_rejects_bad_descriptors():
         bf.stream_schedule([], 5, bf.STREAM_MAX_SLOTS + 1, PSB, PSB)
     with pytest.raises(bf.BeamformError):
         bf.stream_schedule([], 5, 4, PSB, 4 * PSB, depth=0)
+    # warm-up frames left out of the statistics: 0 .. n_frames
+    for bad in (-1, 6):
+        with pytest.raises(bf.BeamformError):
+            bf.stream_schedule([], 5, 4, PSB, 4 * PSB, warmup_frames=bad)
+    for ok in (0, 5):
+        bf.stream_schedule([], 5, 4, PSB, 4 * PSB, warmup_frames=ok)
