@@ -246,6 +246,13 @@ def test_config1_full_size_all_outputs(torch_mod, bfm, config1_data, config1_ref
     print("config1 all %d outputs %s: max %.3e p99.9 %.3e p99 %.3e mean %.3e"
           % (err.size, precision, err.max(), p999, p99, err.mean()))
     assert err.max() <= TOL[precision]
+    # The tolerance bounds the worst output.  These bound the bulk of the
+    # distribution at about twice the measured p99.9 and mean (FP32 4.2e-7 / 1.1e-7,
+    # FP16-MFMA 3.6e-4 / 4.6e-5, FP32-class 5.9e-7 / 1.4e-7), so that a loss of
+    # precision that leaves the worst case inside the tolerance still fails, such
+    # as the FP16 hi + lo operands of the matrix-core stages losing their lo halves.
+    bulk = {"fp32": (1e-6, 3e-7), "fp16": (7e-4, 1e-4), "fp32_mfma": (1.2e-6, 3e-7)}[precision]
+    assert p999 <= bulk[0] and err.mean() <= bulk[1]
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
