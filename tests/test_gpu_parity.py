@@ -84,12 +84,13 @@ def test_other_frame_lengths(torch_mod, bfm, oracle_mod, n_time, precision):
     freqs = np.array([433.2e6, 777.7e6])
     got = _run(torch_mod, bfm, raw, freqs, precision=precision)
     ref = oracle_mod.beamform(oracle_mod.Geometry(n_time=n_time), freqs, raw)
-    if precision != "fp16":
+    if precision != "fp16" or n_time >= 384:
         err = _rel(got, ref)
     else:
-        # Short integrations (2 n_time / 16 terms per output) leave some outputs far
-        # below the median, where FP16 rounding's fixed absolute error is a large
-        # relative one; the 2e-3 relative bar is stated for full 0.983 ms frames.
+        # Frames shorter than 0.983 ms (2 or 6 integrated terms per output) leave
+        # some outputs far below the median, where FP16 rounding's fixed absolute
+        # error is a large relative one; the 2e-3 per-output bar is stated for
+        # frames of at least 384 samples, and n_time = 400 is held to it plainly.
         err = np.abs(got - ref) / np.maximum(ref, np.median(ref))
     print("n_time %d %s max err %.3e" % (n_time, precision, err.max()))
     assert err.max() <= TOL[precision]
@@ -209,14 +210,27 @@ def test_invariants_duplicates_subsets_determinism(torch_mod, bfm, precision):
     assert len(np.unique(lut[1])) < 256  # 600 MHz does alias
 
 
-def test_pol_swap_symmetry(torch_mod, bfm):
-    """Stokes I is symmetric in the two polarisations (same spatial weights)."""
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("sin_phi", [None, (-0.5, -0.1, 0.25, 0.7)])
+def test_pol_swap_symmetry(torch_mod, bfm, precision, sin_phi):
+    """Stokes I is symmetric in the two polarisations (same spatial weights): swapping
+    X and Y in every input gives the same beams.  The FP32 FFT path transforms each
+    polarisation with identical code in its own lanes and adds the two per-bin powers
+    once at the end, and a + b == b + a in floating point, so it is bitwise
+    symmetric.  The matrix-core paths add the two polarisations' powers into one
+    accumulator in turn, block after block, so the swap changes the order of the
+    additions: equal to within the path's tolerance."""
     raw = synth.noise_frames(10, 1, 2)
     sw = raw.reshape(1, 2, 384, 1024, 2)[..., ::-1].reshape(raw.shape)
     freqs = [500e6, 700e6]
-    a = _run(torch_mod, bfm, raw, freqs)
-    b = _run(torch_mod, bfm, np.ascontiguousarray(sw), freqs)
-    assert _rel(a, b).max() <= 1e-6
+    kw = {} if sin_phi is None else {"sin_phi_ew": np.sin(np.deg2rad(sin_phi))}
+    a = _run(torch_mod, bfm, raw, freqs, precision=precision, **kw)
+    b = _run(torch_mod, bfm, np.ascontiguousarray(sw), freqs, precision=precision, **kw)
+    print("pol swap %s %s: max rel diff %.3e" % (precision, sin_phi, _rel(a, b).max()))
+    if precision == "fp32":
+        np.testing.assert_array_equal(a, b)
+    else:
+        assert _rel(a, b).max() <= TOL[precision]
 
 
 @pytest.fixture(scope="module")

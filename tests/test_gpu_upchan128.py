@@ -168,6 +168,31 @@ def test_config4_sky_parity(torch_mod, bfm, oracle_mod, precision):
     assert err.max() <= TOLS[precision]
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp32_mfma"])
+def test_tone_grouping_parity(torch_mod, bfm, oracle_mod, precision):
+    """Noiseless tones on exact fine-channel frequencies, -5 .. +12 fine channels from
+    several sub-channel centres (Sec. 3, Sec. 3.2): each lands in the sub-channel
+    whose 8-fine-channel group holds its frequency (the group nearest the tone,
+    its centre 1.5 kHz below the sub-channel's nominal centre), as the oracle pin
+    derives from frequencies alone, and every output matches the oracle.  The
+    frames hold exact Dirichlet-like nulls, so the error is taken against the
+    frame's largest power."""
+    import test_oracle_pins as pins
+    f = 600e6
+    raw = pins.tone_frames(pins.TONE_CASES, f)
+    freqs = [f] * len(pins.TONE_CASES)
+    got = _run(torch_mod, bfm, raw, freqs, 128, precision=precision)
+    ref = oracle_mod.beamform_upchan128(oracle_mod.Geometry(), freqs, raw)
+    err = np.abs(got - ref) / ref.max(axis=(2, 3), keepdims=True)
+    print("upchan128 tones %s: max err / frame max %.3e" % (precision, err.max()))
+    assert err.max() <= TOLS[precision]
+    tot = got[0].sum(axis=1)
+    for i, (q, off) in enumerate(pins.TONE_CASES):
+        want = pins.expected_subchannel((q - 8) * synth.SUBCHAN_HZ + off * pins.FINE_HZ)
+        assert int(np.argmax(tot[i])) == want, (q, off)
+        assert tot[i, want] >= 0.99 * tot[i].sum(), (q, off)
+
+
 def test_unsupported_configurations(torch_mod, bfm):
     short = torch_mod.zeros((1, 1, 48, 2048), dtype=torch_mod.uint8, device="cuda")
     with bfm.Beamformer([600e6], n_time=48) as b:

@@ -61,9 +61,18 @@ MUTANTS = [
      "if (x > 255.0f) x = 255.0f;", "if (x > 254.0f) x = 254.0f;"),
     ("fine bins grouped without centring",
      "int32_t q = ((qf + G / 2) / G) % nq;", "int32_t q = (qf / G) % nq;"),
+    ("fine bins grouped one fine channel high",
+     "int32_t q = ((qf + G / 2) / G) % nq;", "int32_t q = ((qf + G / 2 - 1) / G) % nq;"),
     ("beam index N-S major",
      "out[((size_t)j * NM + m) * L + q] +=", "out[((size_t)m * NJ + j) * L + q] +="),
 ]
+
+# Mistakes that a pin stated from the paper (not a restatement of the oracle's own
+# rule) must catch: mutant name -> that pin.
+REQUIRED_CATCHER = {
+    "fine bins grouped without centring": "test_upchan128_tone_grouping",
+    "fine bins grouped one fine channel high": "test_upchan128_tone_grouping",
+}
 
 PIN_TESTS = [(name, fn) for name, fn in inspect.getmembers(pins, inspect.isfunction)
              if name.startswith("test_")]
@@ -105,6 +114,8 @@ def test_pins_catch_planted_mistakes(tmp_path):
         print("%s: caught by %s" % (name, failed))
         if not failed:
             missed.append(name)
+        if name in REQUIRED_CATCHER and REQUIRED_CATCHER[name] not in failed:
+            missed.append("%s (not by %s)" % (name, REQUIRED_CATCHER[name]))
     assert not missed, "no pin detects: %s" % missed
 
 

@@ -477,3 +477,53 @@ def test_upchan128_dc_tone_and_parseval(oracle_mod):
     t16 = oracle_mod.beamform(g, [450e6], rnd)[0, 0].sum(axis=1)
     t128 = oracle_mod.beamform_upchan128(g, [450e6], rnd)[0, 0].sum(axis=1)
     assert np.allclose(t128, 8 * t16, rtol=1e-12, atol=0)
+
+
+# Tones on exact fine-channel frequencies: fine channel spacing 390.625 kHz / 128.
+FINE_HZ = synth.CHAN_BW_HZ / 128
+# (sub-channel whose centre the tone is placed near, offset in fine channels)
+TONE_CASES = [(3, -5), (3, -4), (3, -1), (3, 0), (3, 3), (3, 4), (11, 8), (11, 11),
+              (11, 12), (0, -4), (15, 3)]
+
+
+def tone_frames(cases, f_hz, amp=6.0):
+    """One noiseless frame per case: a point source whose tone sits `off` fine
+    channels from the centre of sub-channel q (offset (q - 8) x 24.4 kHz from the
+    channel centre).  A tone on a fine-channel frequency completes a whole number
+    of cycles per 128-sample block, so it falls in one fine channel."""
+    raw = np.empty((1, len(cases), 384, 2048), np.uint8)
+    for i, (q, off) in enumerate(cases):
+        nu = (q - 8) * synth.SUBCHAN_HZ + off * FINE_HZ
+        src = [synth.Source(sin_theta=0.3, phi_deg=0.2, amp=amp, tone_hz=nu, phase=0.4)]
+        synth.channel_frames(None, f_hz, 1, src, raw[:, i], sigma=0.0)
+    return raw
+
+
+def expected_subchannel(nu_hz):
+    """The sub-channel a tone at offset nu from the channel centre belongs to in the
+    128-point form, from frequencies alone: each sub-channel collects the 8 fine
+    channels nearest its centre; 8 is even, so the group's own centre sits half a
+    fine channel (1.5 kHz) below the sub-channel's nominal centre (q - 8) x 24.4 kHz.
+    The tone therefore goes to the sub-channel whose group centre is nearest."""
+    centres = (np.arange(16) - 8) * synth.SUBCHAN_HZ - 0.5 * FINE_HZ
+    d = (nu_hz - centres + synth.CHAN_BW_HZ / 2) % synth.CHAN_BW_HZ - synth.CHAN_BW_HZ / 2
+    return int(np.argmin(np.abs(d)))
+
+
+def test_upchan128_tone_grouping(oracle_mod):
+    """Sec. 3 and Sec. 3.2 (fine channels of 3 kHz summed to 24 kHz): tones at fine-
+    channel offsets -5 .. +12 from several sub-channel centres land, with more than
+    99 % of their power, in the sub-channel whose 8-fine-channel group holds their
+    frequency.  Offsets -4 .. +3 stay in the sub-channel they were placed near, +4,
+    +8 and +11 move one up, +12 two, -5 one down, so a grouping shifted or mirrored
+    by even one fine channel fails."""
+    f = 600e6
+    raw = tone_frames(TONE_CASES, f)
+    out = oracle_mod.beamform_upchan128(_geom(oracle_mod), [f] * len(TONE_CASES), raw)
+    tot = out[0].sum(axis=1)  # [case][q], all beams
+    for i, (q, off) in enumerate(TONE_CASES):
+        nu = (q - 8) * synth.SUBCHAN_HZ + off * FINE_HZ
+        want = expected_subchannel(nu)
+        assert want == (q + (off + 4) // 8) % 16  # -4 .. +3 keep q, +4 .. +11 go up one
+        assert int(np.argmax(tot[i])) == want, (q, off, tot[i])
+        assert tot[i, want] >= 0.99 * tot[i].sum(), (q, off)
