@@ -188,6 +188,25 @@ int32_t beamform_frame_u8(bf_plan *plan, const uint8_t *d_in, int32_t n_frames,
 int32_t beamform_frame_tracking(bf_plan *plan, const uint8_t *d_in, int32_t n_frames,
                                 const double *sin_phi_ew, float *d_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and arguments as beamform_frame_tracking, with results equal to
+ * it bit for bit, but the per-channel-frame weight table is a fixed device
+ * array of the library (BF_NOALLOC_MAX_ROWS channel-frames, 2 MiB, one per
+ * GPU, held until the process ends) and its host staging a fixed host array.
+ * The call makes no device or host allocation (the array's device address is
+ * looked up once per device by beamform_init).  It uploads the weights on
+ * `stream`, launches, and returns once the upload has read the staging table,
+ * i.e. after all work enqueued on `stream` before the call has finished.
+ * Every call on one GPU shares that GPU's table and keeps it until the next
+ * call: calls that overlap on one GPU (other streams, other plans, other host
+ * threads) race, so issue them on one stream.
+ * Errors: BF_E_INVAL when n_frames x n_chan > BF_NOALLOC_MAX_ROWS and for the
+ * arguments beamform_frame_tracking rejects; BF_E_DEVICE. */
+#define BF_NOALLOC_MAX_ROWS 16384
+int32_t beamform_frame_tracking_noalloc(bf_plan *plan, const uint8_t *d_in, int32_t n_frames,
+                                        const double *sin_phi_ew, float *d_out, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Streaming (serving) loop.  Frames of 0.983 ms arrive for a varying set of
  * channels (channels join and leave); each launch beamforms the active

@@ -30,7 +30,7 @@ N_BEAM_NS = 256
 EXPORTED = (
     "beamform_default_config", "beamform_compute_lut", "beamform_init", "beamform_frame",
     "beamform_frame_upchan128", "beamform_frame_u8", "beamform_frame_tracking",
-    "beamform_debug_ns",
+    "beamform_frame_tracking_noalloc", "beamform_debug_ns",
     "beamform_stream", "beamform_stream_schedule", "beamform_get_lut", "beamform_plan_info",
     "beamform_destroy", "beamform_strerror", "beamform_last_error",
 )
@@ -152,6 +152,7 @@ def load_library():
         "beamform_init": ([cp, vp, i32, vp, ctypes.POINTER(vp)], i32),
         "beamform_frame": ([vp, vp, i32, vp, vp], i32),
         "beamform_frame_tracking": ([vp, vp, i32, vp, vp, vp], i32),
+        "beamform_frame_tracking_noalloc": ([vp, vp, i32, vp, vp, vp], i32),
         "beamform_frame_u8": ([vp, vp, i32, vp, vp, vp, vp], i32),
         "beamform_frame_upchan128": ([vp, vp, i32, vp, vp], i32),
         "beamform_debug_ns": ([vp, vp, vp, vp], i32),
@@ -274,12 +275,14 @@ class Beamformer:
     def out_shape(self, n_frames: int):
         return (n_frames, self.n_chan, N_BEAMS, N_UPCHAN)
 
-    def frame(self, raw, out=None, stream=None, sin_phi_ew=None, upchan=16):
+    def frame(self, raw, out=None, stream=None, sin_phi_ew=None, upchan=16, noalloc=False):
         """Beamform raw [n_frames][n_chan][n_time][2048] (CUDA uint8) into out
         [n_frames][n_chan][1024][16] (CUDA float32).  sin_phi_ew: None for the plan's
         static E-W beams, or [n_frames][4] E-W directions per frame (tracking beams).
         upchan: 16 (16-point DFT of 16-sample blocks) or 128 (the 128-point
-        up-channelisation integrated to the same 16 sub-channels)."""
+        up-channelisation integrated to the same 16 sub-channels).  noalloc (tracking
+        beams only): use the entry point whose weight table is the library's fixed
+        device array (no allocation in the call)."""
         import torch
         if self._plan is None:
             raise BeamformError(-4, "plan destroyed")
@@ -299,6 +302,8 @@ class Beamformer:
                              % (self.out_shape(n_frames),))
         if upchan not in (16, 128):
             raise ValueError("upchan must be 16 or 128")
+        if noalloc and sin_phi_ew is None:
+            raise ValueError("noalloc applies to tracking beams (sin_phi_ew)")
         if upchan == 128:
             if sin_phi_ew is not None:
                 raise ValueError("tracking beams use the 16-point up-channelisation")
@@ -312,8 +317,9 @@ class Beamformer:
             phi = np.ascontiguousarray(sin_phi_ew, dtype=np.float64)
             if phi.shape != (n_frames, 4):
                 raise ValueError("sin_phi_ew must be [n_frames][4], got %s" % (phi.shape,))
-            st = self.lib.beamform_frame_tracking(
-                self._plan, ctypes.c_void_p(raw.data_ptr()), n_frames,
+            fn = (self.lib.beamform_frame_tracking_noalloc if noalloc
+                  else self.lib.beamform_frame_tracking)
+            st = fn(self._plan, ctypes.c_void_p(raw.data_ptr()), n_frames,
                 ctypes.c_void_p(phi.ctypes.data), ctypes.c_void_p(out.data_ptr()),
                 _stream_handle(stream))
         _check(st, self._plan)

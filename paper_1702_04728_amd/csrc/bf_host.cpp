@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -188,6 +189,36 @@ int32_t check_batch(bf_plan* p, const uint8_t* d_in, int32_t n_frames, const voi
     return BF_OK;
 }
 
+// Per-frame E-W directions of a tracking call: finite, and whether every
+// frame keeps the mirror symmetry the kernels' cheapest E-W form needs.
+int32_t check_tracking(bf_plan* p, const double* sin_phi_ew, int32_t n_frames, bool* sym)
+{
+    if (!sin_phi_ew) return fail(p, BF_E_INVAL, "sin_phi_ew is NULL");
+    *sym = true;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        const double* s = sin_phi_ew + (size_t)f * bf::kBeamEW;
+        for (int j = 0; j < bf::kBeamEW; ++j)
+            if (!std::isfinite(s[j])) return fail(p, BF_E_INVAL, "sin_phi_ew must be finite");
+        *sym = *sym && mirror_symmetric(p->cyl_x.data(), s);
+    }
+    return BF_OK;
+}
+
+// Weights of every channel-frame of a tracking call, FP64 rounded once:
+// row f * n_chan + ch of out.
+void fill_tracking(const bf_plan* p, const double* sin_phi_ew, int32_t n_frames, float2* out)
+{
+    for (int32_t f = 0; f < n_frames; ++f)
+        for (int32_t ch = 0; ch < p->n_chan; ++ch)
+            fill_ew(p->freqs[ch], p->cyl_x.data(), sin_phi_ew + (size_t)f * bf::kBeamEW, p->cfg.c0,
+                    out + ((size_t)f * p->n_chan + ch) * bf::kBeamEW * bf::kCyl);
+}
+
+// Host staging of the allocation-free tracking entry point: pageable, fixed
+// size, one table at a time (the mutex is held until the upload has read it).
+std::mutex g_noalloc_stage_mutex;
+float2 g_noalloc_stage[bf::kNoAllocRows * bf::kBeamEW * bf::kCyl];
+
 }  // namespace
 
 namespace bf {
@@ -340,6 +371,14 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
 
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { int32_t r = hip_fail(nullptr, e, "hipGetDevice"); delete p; return r; }
+    // the fixed table of the allocation-free tracking entry point: its device
+    // address is looked up here, once per device, with this device current
+    if ((e = bf::noalloc_scratch(p->device, &p->d_scratch)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&p->noalloc_upload, hipEventDisableTiming)) != hipSuccess) {
+        int32_t r = hip_fail(nullptr, e, "fixed tracking table");
+        beamform_destroy(p);
+        return r;
+    }
     hipStream_t s = (hipStream_t)stream;
     const size_t lut_b = p->lut.size() * sizeof(int32_t), ew_b = ew.size() * sizeof(float2),
                  tw_b = tw.size() * sizeof(float2);
@@ -485,14 +524,8 @@ int32_t beamform_frame_tracking(bf_plan* p, const uint8_t* d_in, int32_t n_frame
     p->err.clear();
     int32_t st = check_batch(p, d_in, n_frames, d_out);
     if (st != BF_OK || n_frames == 0) return st;
-    if (!sin_phi_ew) return fail(p, BF_E_INVAL, "sin_phi_ew is NULL");
     bool sym = true;
-    for (int32_t f = 0; f < n_frames; ++f) {
-        const double* s = sin_phi_ew + (size_t)f * bf::kBeamEW;
-        for (int j = 0; j < bf::kBeamEW; ++j)
-            if (!std::isfinite(s[j])) return fail(p, BF_E_INVAL, "sin_phi_ew must be finite");
-        sym = sym && mirror_symmetric(p->cyl_x.data(), s);
-    }
+    if ((st = check_tracking(p, sin_phi_ew, n_frames, &sym)) != BF_OK) return st;
     const size_t rows = (size_t)n_frames * p->n_chan, row_b = bf::kBeamEW * bf::kCyl * sizeof(float2);
     bf_plan::EwTrack& t = p->ew_track[p->ew_track_next];
     hipError_t e = hipSuccess;
@@ -516,10 +549,7 @@ int32_t beamform_frame_tracking(bf_plan* p, const uint8_t* d_in, int32_t n_frame
         }
         t.cap = rows;
     }
-    for (int32_t f = 0; f < n_frames; ++f)
-        for (int32_t ch = 0; ch < p->n_chan; ++ch)
-            fill_ew(p->freqs[ch], p->cyl_x.data(), sin_phi_ew + (size_t)f * bf::kBeamEW, p->cfg.c0,
-                    t.h + ((size_t)f * p->n_chan + ch) * bf::kBeamEW * bf::kCyl);
+    fill_tracking(p, sin_phi_ew, n_frames, t.h);
     hipStream_t s = (hipStream_t)stream;
     if ((e = hipMemcpyAsync(t.d, t.h, rows * row_b, hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_fail(p, e, "tracking table upload");
@@ -527,6 +557,36 @@ int32_t beamform_frame_tracking(bf_plan* p, const uint8_t* d_in, int32_t n_frame
     if ((e = hipEventRecord(t.done, s)) != hipSuccess && st == BF_OK)
         st = hip_fail(p, e, "hipEventRecord");
     p->ew_track_next ^= 1;
+    return st;
+}
+
+int32_t beamform_frame_tracking_noalloc(bf_plan* p, const uint8_t* d_in, int32_t n_frames,
+                                        const double* sin_phi_ew, float* d_out, void* stream)
+{
+    if (!p) return BF_E_INVAL;
+    p->err.clear();
+    int32_t st = check_batch(p, d_in, n_frames, d_out);
+    if (st != BF_OK || n_frames == 0) return st;
+    bool sym = true;
+    if ((st = check_tracking(p, sin_phi_ew, n_frames, &sym)) != BF_OK) return st;
+    const long long rows = (long long)n_frames * p->n_chan;
+    if (rows > bf::kNoAllocRows)
+        return fail(p, BF_E_INVAL, "n_frames x n_chan = " + std::to_string(rows) +
+                                       " exceeds the fixed tracking table of " +
+                                       std::to_string(bf::kNoAllocRows) + " channel-frames");
+    if (!p->d_scratch || !p->noalloc_upload) return fail(p, BF_E_STATE, "no fixed tracking table");
+    const size_t bytes = (size_t)rows * bf::kBeamEW * bf::kCyl * sizeof(float2);
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(g_noalloc_stage_mutex);
+    fill_tracking(p, sin_phi_ew, n_frames, g_noalloc_stage);
+    hipError_t e = hipMemcpyAsync(p->d_scratch, g_noalloc_stage, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(p, e, "fixed tracking table upload");
+    if ((e = hipEventRecord(p->noalloc_upload, s)) != hipSuccess)
+        return hip_fail(p, e, "hipEventRecord");
+    st = launch_batch(p, d_in, n_frames, d_out, s, p->d_scratch, 1, sym ? 1 : 0);
+    // the staging table is reused by the next call: wait until the upload read it
+    if ((e = hipEventSynchronize(p->noalloc_upload)) != hipSuccess && st == BF_OK)
+        st = hip_fail(p, e, "fixed tracking table upload");
     return st;
 }
 
@@ -559,6 +619,7 @@ int32_t beamform_destroy(bf_plan* p)
     if (p->d_mf) (void)hipFree(p->d_mf);
     if (p->d_fine) (void)hipFree(p->d_fine);
     if (p->d_tw128) (void)hipFree(p->d_tw128);
+    if (p->noalloc_upload) (void)hipEventDestroy(p->noalloc_upload);
     for (bf_plan::EwTrack& t : p->ew_track) {
         if (t.d) (void)hipFree(t.d);
         if (t.h) (void)hipHostFree(t.h);

@@ -83,6 +83,14 @@ struct LaunchArgs {
 // (n_time / 16 block iterations) x 16 sub-channels x 8 lines x 256 beams.
 constexpr size_t kFinePerIter = 16 * 8 * 256;
 
+// Rows (channel-frames) of the fixed E-W weight table of the allocation-free
+// tracking entry point, and the devices whose copy of it can be addressed.
+constexpr int kNoAllocRows = BF_NOALLOC_MAX_ROWS;
+constexpr int kMaxDevices = 64;
+// Device address of the calling device's fixed table (looked up on the first
+// call for that device, which must be current; cached afterwards).
+hipError_t noalloc_scratch(int device, float2** out);
+
 hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream);
 hipError_t launch_mfma(const LaunchArgs& a, hipStream_t stream);
 

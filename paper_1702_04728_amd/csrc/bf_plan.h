@@ -36,5 +36,10 @@ struct bf_plan {
     float2* d_fine = nullptr;
     size_t fine_cap_units = 0;
     float2* d_tw128 = nullptr;
+    // Allocation-free tracking: this device's fixed weight table (library-wide,
+    // not owned by the plan) and the event that tells when its upload has read
+    // the host staging table.
+    float2* d_scratch = nullptr;
+    hipEvent_t noalloc_upload = nullptr;
     std::string err;
 };
