@@ -5,8 +5,10 @@ A step is one beamform_frame launch over one batch: the bench workload is 4
 frequency channels (450, 550, 650, 750 MHz) x 128 frames of 384 samples x
 2048 inputs of 4+4-bit seeded synthetic noise plus 8 point sources (402.7 MB
 resident in HBM before timing), producing 1024 beams x 16 sub-channels per
-channel-frame.  Value = channel-frames per second x 0.98304 ms = frequency
-channels the GPU sustains in real time.
+channel-frame.  Value = channel-frames per second x 0.98304 ms, the batch
+throughput expressed in real-time channels.  The paced figure -- channels whose
+0.983 ms frames the serving loop completes with p99 latency inside the frame
+time (config-4 inputs) -- is under "sustained", per path.
 
 Prints ONE JSON line (rank 0).  The library runs on one GPU (channels would
 shard across GPUs with no exchange): --gpus above 1 exits with a message.
@@ -29,9 +31,6 @@ sys.path.insert(0, ROOT)
 METRIC = "frequency channels sustained in real time, FP32 vs FP16-MFMA; p99 frame latency"
 FRAME_S = 384 * 2.56e-6                 # 0.98304 ms
 BYTES_PER_UNIT = 384 * 2048 + 1024 * 16 * 4  # 851,968 algorithmic HBM bytes per channel-frame
-# 128-point up-channelisation: kept beams of 24 sample phases x 16 sub-channels x
-# 8 lines x 256 N-S beams, complex FP32, between the two passes
-FINE_BYTES_PER_UNIT = 24 * 16 * 8 * 256 * 8
 # Conventional flop count per sample (5 N log2 N FFTs): N-S 8 x 512-point = 184,320,
 # E-W 1024 beams x 2 pols x 4 complex MACs = 65,536, 2048 16-point DFTs = 40,960,
 # detection 8,192.  Times 384 samples per channel-frame.
@@ -41,15 +40,20 @@ FINE_BYTES_PER_UNIT = 24 * 16 * 8 * 256 * 8
 FLOPS_PER_UNIT = {"fp32": 384 * (184_320 + 65_536 + 40_960 + 8_192),
                   "fp16": 384 * 8 * 16_384 * 8,
                   "fp32_mfma": 384 * 8 * 16_384 * 8}
+# The 128-point up-channelisation (FP32 path): 2048 128-point DFTs per 128
+# samples, 5 x 128 x 7 flops each, i.e. 71,680 per sample instead of the 16-point
+# form's 40,960; the matrix-core paths' matrix work is the N-S transform's, as above.
+FLOPS_PER_UNIT_128 = {"fp32": 384 * (184_320 + 65_536 + 71_680 + 8_192),
+                      "fp16": FLOPS_PER_UNIT["fp16"], "fp32_mfma": FLOPS_PER_UNIT["fp32_mfma"]}
 PEAK = {"fp32": (157.3, "TFLOP/s", "alu"),    # MI355X FP32 vector peak (published)
         "fp16": (2500.0, "TFLOP/s", "mfma"),  # MI355X dense FP16 matrix peak
         "fp32_mfma": (2500.0, "TFLOP/s", "mfma")}
 HBM_PEAK_GBS = 8000.0
 KERNEL_NAME = {"fp32": "bf_fp32_kernel<true, false>", "fp16": "bf_mfma_kernel<2, false, false>",
                "fp32_mfma": "bf_mfma_kernel<2, true, false>"}
-# first pass of the 128-point up-channelisation
-FINE_KERNEL_NAME = {"fp32": "bf_fp32_kernel<true, true>", "fp16": "bf_mfma_kernel<2, false, true>",
-                    "fp32_mfma": "bf_mfma_kernel<2, true, true>"}
+# the 128-point up-channelisation (one pass)
+UPCHAN_KERNEL_NAME = {"fp32": "bf_fp32_up128_kernel<true>", "fp16": "bf_mfma_up128_kernel<2, false>",
+                      "fp32_mfma": "bf_mfma_up128_kernel<2, true>"}
 # directions without mirror symmetry (tracking beams) take the general E-W form
 KERNEL_NAME_GENERAL = {"fp32": "bf_fp32_kernel<false, false>", "fp16": "bf_mfma_kernel<1, false, false>",
                        "fp32_mfma": "bf_mfma_kernel<1, true, false>"}
@@ -77,10 +81,11 @@ def source_hash(path_key: str) -> str:
     return h.hexdigest()
 
 
-def traffic_from_profiles(path_key: str, units: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when there is none or the kernel source changed since it was taken."""
-    p = os.path.join(ROOT, "profiles", "traffic_%s_config1.json" % path_key)
+def traffic_from_profiles(path_key: str, units: int, form: str = "config1"):
+    """HBM bytes per call from the committed rocprofv3 counter summary (form
+    "config1": the 16-point kernel; "upchan128_config1": the 128-point call), or
+    None when there is none or the kernel source changed since it was taken."""
+    p = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (path_key, form))
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
@@ -107,9 +112,39 @@ def cpu_baseline(raw, freqs, budget_s: float):
     dt = time.perf_counter() - t0
     rate = done / dt
     return {"value": rate * FRAME_S, "unit": "channels (real time)", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": "%d of %d channel-frames of the same workload (frame-major), %.1f s, "
                       "%.3f channel-frames/s" % (done, len(all_units), dt, rate)}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def device_warmup(torch, seconds: float) -> int:
+    """Untimed device copies for about `seconds`, before anything is timed: a
+    fresh process starts the GPU below its sustained clock, and a real-time
+    beamformer runs at the sustained one.  Returns the copies issued."""
+    n = 256 << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    t0 = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        k += 20
+    del src, dst
+    return k
 
 
 def copy_bandwidth(torch, mib: int = 1024, reps: int = 10) -> float:
@@ -182,28 +217,29 @@ def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None, u8=None, u
     log("%s%s: timed %d steps: %.4f ms/step (events)"
         % (prec, " tracking" if sin_phi is not None else " u8" if u8 else
            " upchan128" if upchan == 128 else "", args.steps, ms_step))
+    # algorithmic bytes: input and output only (any intermediate a path moves
+    # through HBM is traffic, reported under roofline.traffic, not work owed)
     unit_bytes = BYTES_PER_UNIT - (3 * 65536 // 4 if u8 else 0)
-    if upchan == 128:  # the first pass's beams, written once and read once
-        unit_bytes += 2 * FINE_BYTES_PER_UNIT
     kern_s = float(np.mean(per)) * 1e-3
-    flops = FLOPS_PER_UNIT[prec] * units
+    flops = (FLOPS_PER_UNIT_128 if upchan == 128 else FLOPS_PER_UNIT)[prec] * units
     peak, punit, bound = PEAK[prec]
     achieved = flops / kern_s / 1e12
     kernel = (KERNEL_NAME if sin_phi is None else KERNEL_NAME_GENERAL)[prec]
+    traffic = None
+    if sin_phi is None and not u8:
+        traffic = traffic_from_profiles(prec, units, "upchan128_config1" if upchan == 128
+                                        else "config1")
     if upchan == 128:
-        # two passes moving the beams through HBM: bound by memory, quoted as
-        # algorithmic bytes per call over the call's duration (both passes)
-        peak, punit, bound = HBM_PEAK_GBS, "GB/s", "hbm"
-        achieved = unit_bytes * units / kern_s / 1e9
-        kernel = FINE_KERNEL_NAME[prec] + " + bf_upchan128_kernel"
+        kernel = UPCHAN_KERNEL_NAME[prec]
     return {
         "value": round(units / (ms_step * 1e-3) * FRAME_S, 2),
         "ms_per_step": round(ms_step, 5),
         "dtype": DTYPE[prec],
         "roofline": {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
                      "unit": punit, "frac": round(achieved / peak, 4),
-                     "traffic": (traffic_from_profiles(prec, units)
-                                 if sin_phi is None and not u8 and upchan == 16 else None),
+                     "traffic": traffic,
+                     "traffic_ratio": (round(traffic / (unit_bytes * units), 3)
+                                       if traffic else None),
                      "kernel": kernel, "flops_per_launch": flops},
         "hbm": {"achieved_GBs": round(unit_bytes * units / kern_s / 1e9, 1),
                 "peak_GBs": HBM_PEAK_GBS,
@@ -215,27 +251,44 @@ def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None, u8=None, u
     }
 
 
-def serve(torch, bf, synth, prec, n_frames: int):
+def serve(torch, bf, synth, prec, n_frames: int, to_clamps: bool = False):
     """Serving loop (config 3): seeded churn of 16-128 channels from 1024 ids, 0.983 ms
     frames paced in real time, hipGraph replay; input ring of 8 frames x 128 slots
-    (805 MB, larger than the 256 MB Infinity Cache) tiled from 16 seeded frames."""
+    (805 MB, larger than the 256 MB Infinity Cache) tiled from 16 seeded frames.
+    to_clamps: start at 120 channels and drift up, down and up again so that the run
+    spends frames at both the 128- and the 16-channel clamp (latency reported per
+    active count at the two ends)."""
     depth, slots = 8, 128
-    events, clamped = synth.churn_events(1003, n_frames)
+    if to_clamps:
+        rj, rl = synth.churn_rates_to_clamps(n_frames)
+        events, clamped = synth.churn_events(1013, n_frames, initial=120, rate_join=rj,
+                                             rate_leave=rl)
+    else:
+        events, clamped = synth.churn_events(1003, n_frames)
     pool = torch.from_numpy(synth.frame_pool(1003, 16)).cuda()
     idx = torch.tensor([(5 * k + 3 * s) % 16 for k in range(depth) for s in range(slots)],
                        device="cuda")
     ring = pool[idx].reshape(depth, slots, 384, 2048).contiguous()
     out = torch.empty((depth, slots, 1024, 16), dtype=torch.float32, device="cuda")
     del pool
+    lat = np.zeros(n_frames)
     with bf.Beamformer([600e6], precision=prec) as b:
-        st, _ = b.stream(ring, out, events, n_frames, pacing=True, use_graph=True,
-                         log_slots=False)
+        st, slot_log = b.stream(ring, out, events, n_frames, pacing=True, use_graph=True,
+                                log_slots=True, latency_log=lat)
     torch.cuda.synchronize()
     del ring, out
-    log("%s serving: p50 %.3f ms p99 %.3f ms max %.3f ms late %d/%d" % (
-        prec, st["latency_p50_ms"], st["latency_p99_ms"], st["latency_max_ms"],
-        st["late_frames"], st["frames"]))
+    n_act = (slot_log >= 0).sum(axis=1)
+    log("%s serving%s: p50 %.3f ms p99 %.3f ms max %.3f ms late %d/%d" % (
+        prec, " to clamps" if to_clamps else "", st["latency_p50_ms"], st["latency_p99_ms"],
+        st["latency_max_ms"], st["late_frames"], st["frames"]))
+    by_active = {}
+    for k in (int(n_act.max()), int(n_act.min())):
+        sel = lat[n_act == k]
+        by_active[str(k)] = {"frames": int(sel.size),
+                             "latency_p50_ms": round(float(np.percentile(sel, 50)), 4),
+                             "latency_p99_ms": round(float(np.percentile(sel, 99)), 4)}
     return {"frames": st["frames"], "budget_ms": 0.98304,
+            "latency_by_active_channels": by_active,
             "latency_p50_ms": round(st["latency_p50_ms"], 4),
             "latency_p99_ms": round(st["latency_p99_ms"], 4),
             "latency_max_ms": round(st["latency_max_ms"], 4),
@@ -248,19 +301,25 @@ def serve(torch, bf, synth, prec, n_frames: int):
             "channel_frames": st["channel_frames"], "wall_s": round(st["wall_s"], 3)}
 
 
-def sweep(torch, bf, synth, prec, n_list, n_frames: int, chunk: int = 0, warmup: int = 200):
+def sweep(torch, bf, synth, prec, n_list, n_frames: int, chunk: int = 0, warmup: int = 200,
+          descend: bool = True):
     """Config 4: N channels spread over 400-800 MHz (c_idx = floor((i + 1/2) 1024 / N)),
     all active, frames paced in real time through the serving loop, ingested in chunks
     of `chunk` samples (0: whole frames); N is sustained when the p99 frame latency of
     the frames after the first `warmup` stays within the 0.983 ms budget.  Input ring:
     4 frames per slot tiled from 16 seeded config-4 frames (noise, DM-500 pulse, RFI
-    tones)."""
+    tones).  The points run in ascending order until one fails; if the first fails,
+    N steps down by 64 until one holds (descend)."""
     pool_c = synth.sweep_c_idx(16)
     pool_np = synth.config4_frames(1004, pool_c, [0]).reshape(16, 384, 2048)
     pool = torch.from_numpy(pool_np).cuda()
     rows = []
     best = 0
-    for n in n_list:
+    n_list = list(n_list)
+    k = 0
+    while k < len(n_list):
+        n = n_list[k]
+        k += 1
         depth = 4
         idx = torch.tensor([(7 * k + s) % 16 for k in range(depth) for s in range(n)],
                            device="cuda")
@@ -286,10 +345,28 @@ def sweep(torch, bf, synth, prec, n_list, n_frames: int, chunk: int = 0, warmup:
             "sustained" if ok else "not sustained"))
         if ok:
             best = max(best, n)
+        elif best == 0 and n - 64 >= 64 and descend:
+            n_list.insert(k, n - 64)  # the first point failed: step down until one holds
         else:
             break
     return {"max_channels_sustained": best, "frames_per_point": n_frames,
             "warmup_frames": warmup, "chunk_samples": chunk or 384, "points": rows}
+
+
+def sustained_summary(sw):
+    """Channels sustained in real time under pacing (the largest sweep point whose
+    p99 frame latency stays within 0.983 ms) with that point's latency figures."""
+    if not sw:
+        return None
+    pt = next((r for r in sw["points"] if r["channels"] == sw["max_channels_sustained"]), None)
+    return {"channels": sw["max_channels_sustained"],
+            "latency_p50_ms": pt["latency_p50_ms"] if pt else None,
+            "latency_p99_ms": pt["latency_p99_ms"] if pt else None,
+            "service_p99_ms": pt["service_p99_ms"] if pt else None,
+            "criterion": "p99 frame latency <= 0.98304 ms over %d paced frames after %d "
+                         "warm-up frames" % (sw["frames_per_point"] - sw["warmup_frames"],
+                                             sw["warmup_frames"]),
+            "points_tried": [r["channels"] for r in sw["points"]]}
 
 
 def main():
@@ -311,14 +388,18 @@ def main():
                     help="skip the 128-point up-channelisation measurement")
     ap.add_argument("--serve-frames", type=int, default=10000,
                     help="frames of the paced serving loop per path (0 skips it)")
-    ap.add_argument("--sweep", action="store_true",
-                    help="also run the max-load sweep (config 4) for each path")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the paced max-load sweep (config 4)")
     ap.add_argument("--sweep-frames", type=int, default=2200)
     ap.add_argument("--sweep-warmup", type=int, default=200,
                     help="frames at the start of each sweep point left out of its statistics")
     ap.add_argument("--sweep-chunk", type=int, default=0,
                     help="samples per serving-loop launch in the sweep (0: whole frames)")
-    ap.add_argument("--sweep-list", default="64,128,192,256,320,384,448,512,544,576,608,640,704,768")
+    ap.add_argument("--sweep-list", default="512,576,640,704",
+                    help="channel counts of the paced sweep, ascending (the full sweep: "
+                         "64,128,192,256,320,384,448,512,544,576,608,640,704,768)")
+    ap.add_argument("--warmup-seconds", type=float, default=1.5,
+                    help="untimed device copies before the first timed launch")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -346,6 +427,8 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     raw = torch.from_numpy(raw_np).to(dev)
+    if args.warmup_seconds > 0:
+        log("device warm-up: %d untimed 256 MiB copies" % device_warmup(torch, args.warmup_seconds))
     paths = ["fp32", "fp16", "fp32_mfma"] if args.precision == "all" else [args.precision]
     results = {}
     for prec in paths:
@@ -397,8 +480,10 @@ def main():
     if args.serve_frames > 0:
         for prec in paths:
             results[prec]["serving"] = serve(torch, bf, synth, prec, args.serve_frames)
+            results[prec]["serving_to_clamps"] = serve(torch, bf, synth, prec, args.serve_frames,
+                                                       to_clamps=True)
 
-    if args.sweep:
+    if not args.no_sweep:
         n_list = [int(v) for v in args.sweep_list.split(",")]
         for prec in paths:
             results[prec]["sweep"] = sweep(torch, bf, synth, prec, n_list, args.sweep_frames,
@@ -408,7 +493,7 @@ def main():
     res = {
         "metric": METRIC,
         "value": head["value"],
-        "unit": "channels (real time)",
+        "unit": "channels (real-time equivalent: batch channel-frames/s x 0.983 ms)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -429,6 +514,8 @@ def main():
         "step_ms_p50": head["step_ms_p50"],
         "step_ms_p99": head["step_ms_p99"],
         "p99_frame_latency_ms": head.get("serving", {}).get("latency_p99_ms"),
+        "sustained": {PATH_NAME[p]: sustained_summary(results[p].get("sweep"))
+                      for p in paths if "sweep" in results[p]},
         "paths": {PATH_NAME[p]: results[p] for p in paths},
     }
     if not args.no_cpu_baseline:

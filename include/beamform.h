@@ -128,16 +128,13 @@ int32_t beamform_frame(bf_plan *plan, const uint8_t *d_in, int32_t n_frames, flo
  * 128-sample block: fine bin s' (centre-shifted q' = (s' + 64) mod 128) is
  * squared and summed over both pols and the frame's blocks into sub-channel
  * q = ((q' + 4) / 8) mod 16, the 8 fine channels nearest its centre.
- * Two passes: the beamforming kernel writes every kept beam of every (sample
- * phase, sub-channel) to a plan-owned workspace (6.3 MB per channel-frame of
- * FP32 complex beams, allocated by the first call, so that call cannot be
- * inside a graph capture; about 256 channel-frames or one frame at a time),
- * the second kernel completes the 128-point transforms and integrates.
- * The plan's precision applies to the first pass (the spatial transforms);
- * the stored beams and the second pass are FP32.
+ * One pass, still time first: the 128-point DFT of each block runs on the raw
+ * samples (16 points over the stride-8 samples, twiddles, 8 points over the
+ * sample phase), bin by bin into on-chip slices that then take E-W phasing,
+ * the N-S transform and detection in the plan's precision; nothing but the
+ * input and the output touches device memory, and the call allocates nothing.
  *   d_in, d_out: as beamform_frame (d_out fully overwritten).
- * Needs n_time % 128 == 0 (else BF_E_UNSUPPORTED); BF_E_NOMEM if the workspace
- * cannot be allocated. */
+ * Needs n_time % 128 == 0 (else BF_E_UNSUPPORTED). */
 int32_t beamform_frame_upchan128(bf_plan *plan, const uint8_t *d_in, int32_t n_frames,
                                  float *d_out, void *stream);
 
@@ -245,13 +242,28 @@ typedef struct {
     int32_t use_graph;        /* 1: replay one captured hipGraph per launch; 0: plain launches */
     int64_t mem_cap_bytes;    /* device bytes the stream may use for channel state and its
                                  share of the rings (0: free memory at start); a JOIN that
-                                 would exceed it, or find no free slot, is rejected */
+                                 would exceed it, or find no free slot, is rejected (a JOIN
+                                 of an active id, or with a frequency whose Eq. (1) bins
+                                 cannot be formed, is ignored) */
     const bf_stream_event *events; /* host, sorted by frame; may be NULL if n_events = 0 */
     int32_t n_events;
     int32_t warmup_frames;         /* frames at the start left out of the latency, late-frame
                                       and service statistics (0 .. n_frames) */
     int32_t *slot_log;        /* optional host int32 [n_frames][max_slots]: channel id held
                                  by each slot during each frame, -1 when empty */
+    const uint8_t *ingest_ok; /* optional host u8 [n_frames][max_slots], set by the ingest
+                                 (the paper's data arrive over lossy links): nonzero when
+                                 frame i of slot s arrived complete by its availability
+                                 time; read when the frame's first chunk is launched.  A
+                                 zero (empty or late ring entry) skips that channel-frame:
+                                 its output entry is written as zeros, flagged invalid in
+                                 d_out_valid and counted in missing_frames.  NULL: every
+                                 frame arrived */
+    uint8_t *d_out_valid;     /* optional device u8 [depth][max_slots]: written with the
+                                 output entry of every active slot, 1 = beamformed,
+                                 0 = zeros for a missing frame */
+    double *latency_log_ms;   /* optional host [n_frames]: each frame's latency in ms
+                                 (warm-up frames included), filled before returning */
 } bf_stream_desc;
 
 typedef struct {
@@ -271,6 +283,8 @@ typedef struct {
     int64_t per_slot_bytes;    /* device bytes one active channel costs */
     int32_t slot_capacity;     /* slots admissible under mem_cap_bytes */
     int32_t reserved;
+    int64_t missing_frames;    /* active channel-frames skipped (ingest_ok zero), output
+                                  zeroed and flagged; all frames, warm-up included */
 } bf_stream_stats;
 
 /* Run the serving loop on the plan's geometry and precision (the plan's own

@@ -74,7 +74,10 @@ class BfStreamDesc(ctypes.Structure):
                 ("mem_cap_bytes", ctypes.c_int64),
                 ("events", ctypes.POINTER(BfStreamEvent)), ("n_events", ctypes.c_int32),
                 ("warmup_frames", ctypes.c_int32),
-                ("slot_log", ctypes.POINTER(ctypes.c_int32))]
+                ("slot_log", ctypes.POINTER(ctypes.c_int32)),
+                ("ingest_ok", ctypes.POINTER(ctypes.c_uint8)),
+                ("d_out_valid", ctypes.c_void_p),
+                ("latency_log_ms", ctypes.POINTER(ctypes.c_double))]
 
 
 class BfStreamStats(ctypes.Structure):
@@ -88,7 +91,8 @@ class BfStreamStats(ctypes.Structure):
                 ("service_mean_ms", ctypes.c_double), ("service_p99_ms", ctypes.c_double),
                 ("wall_s", ctypes.c_double), ("channels_realtime", ctypes.c_double),
                 ("input_gb_s", ctypes.c_double), ("per_slot_bytes", ctypes.c_int64),
-                ("slot_capacity", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("slot_capacity", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("missing_frames", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
@@ -104,7 +108,8 @@ def _events_array(events):
 
 
 def _stream_desc(depth, max_slots, n_frames, chunk, pacing, use_graph, mem_cap_bytes, events,
-                 slot_log, d_in=None, d_out=None, warmup_frames=0):
+                 slot_log, d_in=None, d_out=None, warmup_frames=0, ingest_ok=None,
+                 d_out_valid=None):
     arr, n_ev = _events_array(events)
     d = BfStreamDesc()
     d.d_in_ring = d_in
@@ -116,16 +121,25 @@ def _stream_desc(depth, max_slots, n_frames, chunk, pacing, use_graph, mem_cap_b
     d.warmup_frames = int(warmup_frames)
     if slot_log is not None:
         d.slot_log = slot_log.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-    return d, arr
+    keep = [arr]
+    if ingest_ok is not None:
+        ok = np.ascontiguousarray(ingest_ok, dtype=np.uint8)
+        if ok.shape != (n_frames, max_slots):
+            raise ValueError("ingest_ok must be [n_frames][max_slots] = %s, got %s"
+                             % ((n_frames, max_slots), ok.shape))
+        keep.append(ok)
+        d.ingest_ok = ok.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    d.d_out_valid = d_out_valid
+    return d, keep
 
 
 def stream_schedule(events, n_frames, max_slots, per_slot_bytes, cap_bytes, depth=1,
-                    warmup_frames=0):
+                    warmup_frames=0, ingest_ok=None):
     """Host-only dry run of the serving loop's scheduler: (stats dict, slot_log)."""
     lib = load_library()
     log = np.full((n_frames, max_slots), -1, dtype=np.int32)
     d, keep = _stream_desc(depth, max_slots, n_frames, 0, 0, 0, 0, events, log,
-                           warmup_frames=warmup_frames)
+                           warmup_frames=warmup_frames, ingest_ok=ingest_ok)
     st = BfStreamStats()
     _check(lib.beamform_stream_schedule(ctypes.byref(d), int(per_slot_bytes), int(cap_bytes),
                                         ctypes.byref(st)))
@@ -376,11 +390,16 @@ class Beamformer:
         return out
 
     def stream(self, in_ring, out_ring, events, n_frames, chunk=0, pacing=False, use_graph=True,
-               mem_cap_bytes=0, stream=None, log_slots=True, warmup_frames=0):
+               mem_cap_bytes=0, stream=None, log_slots=True, warmup_frames=0, ingest_ok=None,
+               out_valid=None, latency_log=None):
         """Run the serving loop (blocking).  in_ring: CUDA uint8 [depth][max_slots][n_time][2048];
         out_ring: CUDA float32 [depth][max_slots][1024][16]; events: (frame, op, channel_id,
         freq_hz) tuples sorted by frame; latency and service statistics leave out the first
-        warmup_frames frames.  Returns (stats dict, slot_log [n_frames][max_slots])."""
+        warmup_frames frames.  ingest_ok: host uint8 [n_frames][max_slots], 0 where a
+        channel-frame did not arrive (its output is zeroed and flagged); out_valid: CUDA
+        uint8 [depth][max_slots] receiving those flags; latency_log: host float64
+        [n_frames] receiving each frame's latency in ms.  Returns (stats dict, slot_log
+        [n_frames][max_slots])."""
         import torch
         if not (isinstance(in_ring, torch.Tensor) and in_ring.is_cuda and in_ring.dtype == torch.uint8
                 and in_ring.is_contiguous() and in_ring.dim() == 4
@@ -393,10 +412,23 @@ class Beamformer:
                 and tuple(out_ring.shape) == (depth, max_slots, N_BEAMS, N_UPCHAN)):
             raise ValueError("out_ring must be a contiguous CUDA float32 [%d][%d][%d][%d]"
                              % (depth, max_slots, N_BEAMS, N_UPCHAN))
+        if out_valid is not None and not (
+                isinstance(out_valid, torch.Tensor) and out_valid.is_cuda
+                and out_valid.dtype == torch.uint8 and out_valid.is_contiguous()
+                and tuple(out_valid.shape) == (depth, max_slots)):
+            raise ValueError("out_valid must be a contiguous CUDA uint8 [%d][%d]"
+                             % (depth, max_slots))
         log = np.full((n_frames, max_slots), -1, dtype=np.int32) if log_slots else None
         d, keep = _stream_desc(depth, max_slots, n_frames, chunk, pacing, use_graph,
                                mem_cap_bytes, events, log, ctypes.c_void_p(in_ring.data_ptr()),
-                               ctypes.c_void_p(out_ring.data_ptr()), warmup_frames)
+                               ctypes.c_void_p(out_ring.data_ptr()), warmup_frames, ingest_ok,
+                               ctypes.c_void_p(out_valid.data_ptr()) if out_valid is not None
+                               else None)
+        if latency_log is not None:
+            if not (isinstance(latency_log, np.ndarray) and latency_log.dtype == np.float64
+                    and latency_log.flags.c_contiguous and latency_log.shape == (n_frames,)):
+                raise ValueError("latency_log must be a contiguous float64 array [%d]" % n_frames)
+            d.latency_log_ms = latency_log.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         st = BfStreamStats()
         rc = self.lib.beamform_stream(self._plan, ctypes.byref(d), ctypes.byref(st),
                                       _stream_handle(stream))

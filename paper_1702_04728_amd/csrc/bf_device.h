@@ -151,7 +151,9 @@ __device__ __forceinline__ bool resolve_unit(const LaunchArgs& a, const Work& wk
         return true;
     }
     if (wk.unit >= a.st->n_active) return false;
-    const int slot = a.st->slot[wk.unit];
+    const int32_t sv = a.st->slot[wk.unit];
+    const int slot = sv & kSlotMask;
+    const bool missing = (sv & kSlotMissing) != 0;
     const size_t entry = (size_t)a.st->ring_index * a.max_slots + slot;
     const int chunk = a.st->chunk_index;
     io.in = a.in + (entry * a.n_time + (size_t)chunk * a.n_blk * kUp) * kInputs;
@@ -162,7 +164,9 @@ __device__ __forceinline__ bool resolve_unit(const LaunchArgs& a, const Work& wk
     io.out_u8 = nullptr;
     io.first = chunk == 0;
     io.last = chunk == a.st->n_chunks - 1;
-    return true;
+    // a missing frame has no input to read; bf_stream_flags_kernel zeroes its
+    // output entry and writes every active entry's valid flag
+    return !missing;
 }
 
 // Partial per-bin sums of a workgroup, element e of thread t at e * 256 + t.
@@ -293,27 +297,18 @@ __device__ __forceinline__ void load_block(const uint8_t* __restrict__ blk, uint
         raw[tau] = *reinterpret_cast<const uint2*>(blk + tau * stride + 8 * t);
 }
 
-// Samples of block iteration `it`: 16 consecutive samples, or (stride8, the
-// first pass of the 128-point up-channelisation) the samples u + 8 tau of
-// 128-sample block it / 8 with u = it % 8, so that the 16-point time DFT is
-// the first step of a 128-point DFT split as 128 = 16 (tau) x 8 (u).
-__device__ __forceinline__ const uint8_t* block_base(const uint8_t* in, int it, bool stride8)
+// Samples of 16-sample block `it`.
+__device__ __forceinline__ const uint8_t* block_base(const uint8_t* in, int it)
 {
-    return stride8 ? in + (size_t)((it >> 3) * 128 + (it & 7)) * kInputs
-                   : in + (size_t)it * (kUp * kInputs);
-}
-__device__ __forceinline__ int block_stride(bool stride8)
-{
-    return stride8 ? 8 * kInputs : kInputs;
+    return in + (size_t)it * (kUp * kInputs);
 }
 
-// Complex beams out (first pass of the 128-point up-channelisation, or the
-// pre-detection beams): the 512 bins of one line (sub-channel k, line
-// p * 4 + j, block iteration it) sit in LDS at bins[]; the kept beam of every
-// N-S pointing m is bins[lut[m]].  Lane `lane` of 256 / N lanes writes the
-// beams m = lane + (256 / N) i, i < N, whose table entries it holds in
-// registers (read once per kernel by load_lut_lane): a table read inside the
-// line loop would wait, through the shared load/store counter, for every
+// Complex beams out (the pre-detection beams): the 512 bins of one line
+// (sub-channel k, line p * 4 + j, block it) sit in LDS at bins[]; the kept
+// beam of every N-S pointing m is bins[lut[m]].  Lane `lane` of 256 / N lanes
+// writes the beams m = lane + (256 / N) i, i < N, whose table entries it holds
+// in registers (read once per kernel by load_lut_lane): a table read inside
+// the line loop would wait, through the shared load/store counter, for every
 // beam store issued before it.
 template <int N>
 __device__ __forceinline__ void load_lut_lane(const int32_t* __restrict__ lut, int32_t (&lv)[N], int lane)
@@ -328,11 +323,215 @@ __device__ __forceinline__ void write_fine_line(const float2* __restrict__ bins,
 #pragma unroll
     for (int i = 0; i < N; ++i) dst[lane + (kBeamNS / N) * i] = bins[lv[i]];
 }
-// Line (p * 4 + j) of sub-channel k, block iteration it of a unit in the
-// complex-beam buffer.
+// Line (p * 4 + j) of sub-channel k, block it of a unit in the complex-beam
+// buffer.
 __device__ __forceinline__ float2* fine_line_ptr(const LaunchArgs& a, int unit, int it, int k, int line)
 {
     return a.fine + ((((size_t)unit * a.n_blk + it) * 16 + k) * 8 + line) * kBeamNS;
+}
+
+// ---------------------------------------------------------------------------
+// The paper's own up-channelisation (Sec. 3, Sec. 3.2): a 128-point DFT of each
+// 128-sample block, fine bin s' centre-shifted to q' = (s' + 64) mod 128 and
+// its power summed into sub-channel q = ((q' + 4) div 8) mod 16 (the 8 fine
+// channels nearest the sub-channel's centre).
+//
+// Still time first: the 128-point DFT runs on the raw samples, before E-W
+// phasing and the N-S transform.  With s' = k + 16 r (k < 16, r < 8) and
+// t = u + 8 tau (u < 8, tau < 16),
+//   X[k + 16 r] = sum_u w8^(r u) w128^(u k) Y_u[k],  Y_u[k] = sum_tau x[u + 8 tau] w16^(k tau),
+// so one bin k gives 8 fine "slices" r of all 2048 inputs (128 KB as FP32 in
+// LDS), each of which then takes the same E-W and N-S transforms as a 16-point
+// slice.  Fine bin k + 16 r lands in sub-channel q = (2 r + 8 + (k + 4) div 8)
+// mod 16: its parity is fixed by k, so a workgroup of 8 waves takes the 8 bins
+// k of one parity (par 1: k = 4..11, odd q; par 0: k = 0..3, 12..15, even q),
+// and wave w always integrates the one sub-channel q_w = 2 w + 8 + par (mod 16)
+// -- for every k exactly one of its 8 slices lands there.  No partial sums
+// cross workgroups.
+constexpr int kThreads128 = 512;
+
+// Workgroup -> (channel-frame, parity).  The two workgroups of a channel-frame
+// differ only in bit 3 of the id, so they run on the same XCD and share each
+// raw block through its L2.
+struct Work128 {
+    int unit, par;
+};
+__device__ __forceinline__ Work128 work128_of_block()
+{
+    const int x = blockIdx.x;
+    Work128 w;
+    w.par = (x >> 3) & 1;
+    w.unit = ((x >> 4) << 3) | (x & 7);
+    return w;
+}
+inline dim3 grid128_for(int n_units) { return dim3(((n_units + 7) / 8) * 16); }
+
+// Bin k of step i < 8 of a workgroup of parity par.
+__device__ __forceinline__ int k128_of(int par, int i) { return par ? 4 + i : (i < 4 ? i : 8 + i); }
+// Sub-channel of fine bin k + 16 r.
+__device__ __forceinline__ int q128_of(int k, int r) { return ((((k + 16 * r + 64) & 127) + 4) >> 3) & 15; }
+// The slice r of bin k whose fine channel lands in sub-channel q (q of the
+// parity k serves).
+__device__ __forceinline__ int r128_for(int k, int q)
+{
+    int r = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        if (q128_of(k, c) == q) r = c;
+    return r;
+}
+// Sub-channel integrated by wave w of a workgroup of parity par.
+__device__ __forceinline__ int q128_of_wave(int par, int w) { return (2 * w + 8 + par) & 15; }
+
+// In-place DFT-8, natural order: X_r = sum_u x_u w8^(r u).
+__device__ __forceinline__ void dft8(float2 (&x)[8])
+{
+    float2 e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+    float2 o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    // w8^1 = (1 - i)/sqrt2, w8^2 = -i, w8^3 = -(1 + i)/sqrt2
+    o1 = make_float2((o1.x + o1.y) * kR2, (o1.y - o1.x) * kR2);
+    o2 = rot<1>(o2);
+    o3 = make_float2((o3.y - o3.x) * kR2, -(o3.x + o3.y) * kR2);
+    x[0] = cadd(e0, o0);
+    x[4] = csub(e0, o0);
+    x[1] = cadd(e1, o1);
+    x[5] = csub(e1, o1);
+    x[2] = cadd(e2, o2);
+    x[6] = csub(e2, o2);
+    x[3] = cadd(e3, o3);
+    x[7] = csub(e3, o3);
+}
+
+// Bin k (class S0 = k mod 4) of the 128-point DFT of one 128-sample block for
+// this thread's 4 inputs (bytes 4t .. 4t+3 of each sample row: feeds 2t, 2t+1
+// of one cylinder, both pols): the 8 fine slices r go to T[r * 1024 +
+// tslot(slot)], float4 = both pols, slot = cyl * 256 + feed = 2t, 2t + 1.
+//   y_u[t1] = sum_t2 x[u + 8 (t1 + 4 t2)] (-i)^(S0 t2)    (bytewise integer sums)
+//   Z_u     = w128^(u k) Y_u[k] = sum_t1 w128^(k (u + 8 t1)) y_u[t1]
+//   X[r]    = DFT-8 over u of Z_u
+// twk[m] = w128^(k m), m < 32 (host FP64, rounded once).  Every converted
+// value has its bias taken off exactly, so a zero-valued input stays zero.
+// The unit's samples are read through a buffer resource (base and size in
+// SGPRs, bounds-checked by the hardware: reads past `bytes` return 0): one
+// VGPR lane offset and scalar row offsets, where 64-bit per-row addresses
+// would hold 32 VGPRs.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t unit_rsrc(const uint8_t* base, int bytes)
+{
+    // dword 3 of a raw (untyped) buffer descriptor on gfx9-family GPUs
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), 0, bytes, 0x00020000);
+}
+__device__ __forceinline__ uint32_t load_word(__amdgpu_buffer_rsrc_t r, int lane_off, int row_off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, row_off, 0);
+}
+
+template <int S0>
+__device__ __forceinline__ void time_dft128(__amdgpu_buffer_rsrc_t src, int blk_off,
+                                            const float2* __restrict__ twk,
+                                            float4* __restrict__ T, int t)
+{
+    constexpr uint32_t kLo = 0x0f0f0f0fu;
+    constexpr uint32_t kBias = 0x20202020u;
+    float2 Z[8][4];  // [u][input byte e]
+    uint32_t raw[16], nxt[16];
+#pragma unroll
+    for (int tau = 0; tau < 16; ++tau) nxt[tau] = load_word(src, 4 * t, blk_off + 8 * tau * kInputs);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        // one phase u at a time: without the barrier the scheduler hoists every
+        // phase's loads and runs out of registers
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int tau = 0; tau < 16; ++tau) raw[tau] = nxt[tau];
+        if (u < 7) {
+#pragma unroll
+            for (int tau = 0; tau < 16; ++tau)
+                nxt[tau] = load_word(src, 4 * t, blk_off + (u + 1 + 8 * tau) * kInputs);
+        }
+        uint32_t yr[4], yi[4];
+#pragma unroll
+        for (int t1 = 0; t1 < 4; ++t1) {
+            uint32_t r[4], m[4];
+#pragma unroll
+            for (int t2 = 0; t2 < 4; ++t2) {
+                const uint32_t v = raw[t1 + 4 * t2];
+                r[t2] = (v >> 4) & kLo;
+                m[t2] = v & kLo;
+            }
+            // each byte of y = value + 32 (both components)
+            if constexpr (S0 == 0) {
+                yr[t1] = r[0] + r[1] + r[2] + r[3];
+                yi[t1] = m[0] + m[1] + m[2] + m[3];
+            } else if constexpr (S0 == 1) {  // x0 - i x1 - x2 + i x3
+                yr[t1] = add3_u32(r[0], m[1], kBias) - (r[2] + m[3]);
+                yi[t1] = add3_u32(m[0], r[3], kBias) - (r[1] + m[2]);
+            } else if constexpr (S0 == 2) {  // x0 - x1 + x2 - x3
+                yr[t1] = add3_u32(r[0], r[2], kBias) - (r[1] + r[3]);
+                yi[t1] = add3_u32(m[0], m[2], kBias) - (m[1] + m[3]);
+            } else {  // x0 + i x1 - x2 - i x3
+                yr[t1] = add3_u32(r[0], m[3], kBias) - (m[1] + r[2]);
+                yi[t1] = add3_u32(m[0], r[1], kBias) - (m[2] + r[3]);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int t1 = 0; t1 < 4; ++t1) {
+                const float2 y = make_float2(ubyte_to_float(yr[t1], e) - 32.f,
+                                             ubyte_to_float(yi[t1], e) - 32.f);
+                const float2 w = twk[u + 8 * t1];
+                acc = t1 == 0 ? cmul(y, w) : cmac(acc, y, w);
+            }
+            // pins the phase's arithmetic here: otherwise the compiler defers it
+            // to the end and keeps every phase's converted values live instead
+            asm volatile("" : "+v"(acc.x), "+v"(acc.y));
+            Z[u][e] = acc;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        float2 x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = Z[u][e];
+        dft8(x);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) Z[u][e] = x[u];  // Z[r][e] from here on
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        T[r * 1024 + tslot(2 * t)] = make_float4(Z[r][0].x, Z[r][0].y, Z[r][1].x, Z[r][1].y);
+        T[r * 1024 + tslot(2 * t + 1)] = make_float4(Z[r][2].x, Z[r][2].y, Z[r][3].x, Z[r][3].y);
+    }
+}
+
+__device__ __forceinline__ void time_dft128_bin(int k, __amdgpu_buffer_rsrc_t src, int blk_off,
+                                                const float2* twk, float4* T, int t)
+{
+    switch (k & 3) {
+    case 0: time_dft128<0>(src, blk_off, twk, T, t); break;
+    case 1: time_dft128<1>(src, blk_off, twk, T, t); break;
+    case 2: time_dft128<2>(src, blk_off, twk, T, t); break;
+    default: time_dft128<3>(src, blk_off, twk, T, t); break;
+    }
+}
+
+// End of frame, 128-point form: P[(w * 4 + j) * 512 + bin] holds wave w's
+// integrated power of FFT bin `bin`, E-W beam j; beam (j, m) takes bin lut[m]
+// into sub-channel q128_of_wave(par, w).
+__device__ __forceinline__ void write_beams128(const float* __restrict__ P,
+                                               const int32_t* __restrict__ lut,
+                                               float* __restrict__ dst, int par, int t)
+{
+#pragma unroll 4
+    for (int it = 0; it < 16; ++it) {
+        const int u = it * kThreads128 + t;
+        const int beam = u >> 3, w = u & 7;
+        const int jj = beam >> 8, m = beam & 255;
+        dst[beam * kUp + q128_of_wave(par, w)] = P[(w * 4 + jj) * 512 + lut[m]];
+    }
 }
 
 // End of frame: P[(s2 * 4 + j) * 512 + k] holds the integrated power of FFT

@@ -85,8 +85,8 @@ __device__ __forceinline__ void fft16(float2 (&v)[16])
 // Zero-padded 512-point N-S transform of one line held as x[a] = line[16 a + b]
 // by lane b of a 16-lane group; accumulates |X_k|^2 for k = 2 b + r + 32 d into
 // acc[r][d].  bufE / bufO: this group's two transpose buffers (adjacent).
-// kFine: instead, the kept beams of the line go to fine_dst (first pass of the
-// 128-point up-channelisation), gathered through the transpose buffers.
+// kFine: instead, the kept beams of the line go to fine_dst (the pre-detection
+// beams), gathered through the transpose buffers.
 template <bool kFine>
 __device__ __forceinline__ void ns_line_power(const float2 (&x)[16], float (&acc)[2][16],
                                               float2* __restrict__ bufE,
@@ -167,6 +167,41 @@ __device__ __forceinline__ void ns_line_power(const float2 (&x)[16], float (&acc
 }
 static_assert(2 * kXpBuf >= 512, "a group's transpose buffers must hold one line's bins");
 
+// E-W phasing of a 16-lane group: lane b forms feeds 16 a + b of the group's two
+// E-W beams (W[0], W[1]) of one polarisation from one time-DFT slice Tp (stride
+// 2 float2 per slot: the other pol interleaved).  With kSym (mirror-symmetric
+// geometry, the group's beams jp and 3 - jp) the pair shares its cylinder sums.
+template <bool kSym>
+__device__ __forceinline__ void ew_group(const float2* __restrict__ Tp, const float2 (&W)[2][4],
+                                         float2 (&v0)[16], float2 (&v1)[16], int b)
+{
+#pragma unroll
+    for (int aa = 0; aa < 16; ++aa) {
+        float2 y[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) y[c] = Tp[2 * tslot(c * 256 + 16 * aa + b)];
+        if constexpr (kSym) {
+            const float2 S0 = cadd(y[0], y[3]), S1 = cadd(y[1], y[2]);
+            const float2 D0 = csub(y[0], y[3]), D1 = csub(y[1], y[2]);
+            const float2 P = make_float2(fmaf(W[0][0].x, S0.x, W[0][1].x * S1.x),
+                                         fmaf(W[0][0].x, S0.y, W[0][1].x * S1.y));
+            const float2 Q = make_float2(fmaf(W[0][0].y, D0.x, W[0][1].y * D1.x),
+                                         fmaf(W[0][0].y, D0.y, W[0][1].y * D1.y));
+            v0[aa] = make_float2(P.x - Q.y, P.y + Q.x);
+            v1[aa] = make_float2(P.x + Q.y, P.y - Q.x);
+        } else {
+            float2 p0 = make_float2(0.f, 0.f), p1 = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                p0 = cmac(p0, y[c], W[0][c]);
+                p1 = cmac(p1, y[c], W[1][c]);
+            }
+            v0[aa] = p0;
+            v1[aa] = p1;
+        }
+    }
+}
+
 template <bool kSym, bool kFine>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bf_fp32_kernel(LaunchArgs a)
@@ -204,8 +239,7 @@ void bf_fp32_kernel(LaunchArgs a)
     if constexpr (kFine) load_lut_lane<16>(a.lut + (size_t)io.row * kBeamNS, lv, b);
 
     uint2 raw[16];
-    const bool s8 = kFine && a.fine_stride8;
-    load_block(block_base(src, 0, s8), raw, t, block_stride(s8));
+    load_block(block_base(src, 0), raw, t);
 
     float acc[2][2][16];  // [line l: beam jl[l]][E/O][d]
     constexpr int kAcc = sizeof(acc) / sizeof(float);
@@ -224,31 +258,7 @@ void bf_fp32_kernel(LaunchArgs a)
         __syncthreads();
         // B1: E-W phasing while loading this group's feeds 16 a + b of pol p
         float2 v0[16], v1[16];
-#pragma unroll
-        for (int aa = 0; aa < 16; ++aa) {
-            float2 y[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) y[c] = Tp[2 * (s2 * 1024 + tslot(c * 256 + 16 * aa + b))];
-            if constexpr (kSym) {
-                const float2 S0 = cadd(y[0], y[3]), S1 = cadd(y[1], y[2]);
-                const float2 D0 = csub(y[0], y[3]), D1 = csub(y[1], y[2]);
-                const float2 P = make_float2(fmaf(W[0][0].x, S0.x, W[0][1].x * S1.x),
-                                             fmaf(W[0][0].x, S0.y, W[0][1].x * S1.y));
-                const float2 Q = make_float2(fmaf(W[0][0].y, D0.x, W[0][1].y * D1.x),
-                                             fmaf(W[0][0].y, D0.y, W[0][1].y * D1.y));
-                v0[aa] = make_float2(P.x - Q.y, P.y + Q.x);
-                v1[aa] = make_float2(P.x + Q.y, P.y - Q.x);
-            } else {
-                float2 p0 = make_float2(0.f, 0.f), p1 = make_float2(0.f, 0.f);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    p0 = cmac(p0, y[c], W[0][c]);
-                    p1 = cmac(p1, y[c], W[1][c]);
-                }
-                v0[aa] = p0;
-                v1[aa] = p1;
-            }
-        }
+        ew_group<kSym>(Tp + 2 * s2 * 1024, W, v0, v1, b);
         __syncthreads();
         // B2: N-S transform of both lines, power into per-bin accumulators; the
         // next block's samples are fetched during the second line (issued
@@ -258,12 +268,12 @@ void bf_fp32_kernel(LaunchArgs a)
         const int k = wk.s0 + 4 * s2;
         ns_line_power<kFine>(v0, acc[0], bufE, bufO, s_tw, b, lv,
                              kFine ? fine_line_ptr(a, wk.unit, blk, k, pol * 4 + jl[0]) : nullptr);
-        load_block(block_base(src, min(blk + 1, a.n_blk - 1), s8), raw, t, block_stride(s8));
+        load_block(block_base(src, min(blk + 1, a.n_blk - 1)), raw, t);
         ns_line_power<kFine>(v1, acc[1], bufE, bufO, s_tw, b, lv,
                              kFine ? fine_line_ptr(a, wk.unit, blk, k, pol * 4 + jl[1]) : nullptr);
         __syncthreads();
     }
-    if constexpr (kFine) return;  // the second pass detects and integrates
+    if constexpr (kFine) return;  // complex beams only
 
     if (!io.last) {  // frame continues in the next chunk's launch
         store_partial<kAcc>(&acc[0][0][0], io.partial, t);
@@ -295,7 +305,109 @@ void bf_fp32_kernel(LaunchArgs a)
     write_output(P, a, io, wk.s0, t);
 }
 
+// The paper's 128-point up-channelisation in one pass (layout of the fine
+// slices and the wave -> sub-channel map: time_dft128 and Work128).  512
+// threads = 32 groups (wave w = g >> 2, jp, pol); per 128-sample block and per
+// bin k of the workgroup's parity: all threads form the 8 fine slices of bin k
+// (128 KB in LDS), wave w's groups take the slice whose fine channel lands in
+// its sub-channel through E-W phasing and the N-S transform into |X|^2 per bin.
+constexpr int kUnion128F2 = 32 * kGroupF2;       // 32 groups' transposes (17,920 float2)
+static_assert(kUnion128F2 * 8 >= 8 * 1024 * 16, "union region must hold the 8 fine slices");
+static_assert(kUnion128F2 * 8 >= 8 * 4 * 512 * 4, "union region must hold the per-bin powers");
+
+template <bool kSym>
+__global__ __launch_bounds__(kThreads128) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void bf_fp32_up128_kernel(LaunchArgs a)
+{
+    __shared__ __align__(16) float2 s_union[kUnion128F2];
+    __shared__ __align__(16) float4 s_tw[16 * 16];  // [c'][b]: w512^(b 2c'), w512^(b (2c'+1))
+
+    const Work128 wk = work128_of_block();
+    if (wk.unit >= a.n_units) return;  // uniform across the workgroup
+    const int t = threadIdx.x;
+    const int g = t >> 4;
+    const int b = t & 15;
+    const int w = g >> 2, jp = (g >> 1) & 1, pol = g & 1;
+    const int jl[2] = {jp, 3 - jp};
+    const int qw = q128_of_wave(wk.par, w);
+    const int row = wk.unit % a.n_chan;
+
+    if (t < 256) {
+        const int c2 = t >> 4, bb = t & 15;
+        const float2 w0 = a.tw[(2 * c2) * 16 + bb], w1 = a.tw[(2 * c2 + 1) * 16 + bb];
+        s_tw[t] = make_float4(w0.x, w0.y, w1.x, w1.y);
+    }
+    float2 W[2][4];
+#pragma unroll
+    for (int l = 0; l < 2; ++l)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) W[l][c] = a.ew[((size_t)row * kBeamEW + jl[l]) * kCyl + c];
+
+    const __amdgpu_buffer_rsrc_t src = unit_rsrc(a.in + (size_t)wk.unit * a.n_time * kInputs,
+                                                 a.n_time * kInputs);
+    float4* T = reinterpret_cast<float4*>(s_union);
+    const float2* Tp = reinterpret_cast<const float2*>(s_union) + pol;
+    float2* bufE = s_union + g * kGroupF2;
+    float2* bufO = bufE + kXpBuf;
+    const int32_t lv[1] = {0};
+
+    float acc[2][2][16];
+#pragma unroll
+    for (int l = 0; l < 2; ++l)
+#pragma unroll
+        for (int d = 0; d < 16; ++d) acc[l][0][d] = acc[l][1][d] = 0.f;
+
+    const int n_blk128 = a.n_time / 128;
+    for (int blk = 0; blk < n_blk128; ++blk) {
+        for (int i = 0; i < 8; ++i) {
+            const int k = k128_of(wk.par, i);
+            time_dft128_bin(k, src, blk * 128 * kInputs, a.tw128k + k * 32, T, t);
+            __syncthreads();
+            float2 v0[16], v1[16];
+            ew_group<kSym>(Tp + 2 * r128_for(k, qw) * 1024, W, v0, v1, b);
+            __syncthreads();
+            ns_line_power<false>(v0, acc[0], bufE, bufO, s_tw, b, lv, nullptr);
+            ns_line_power<false>(v1, acc[1], bufE, bufO, s_tw, b, lv, nullptr);
+            __syncthreads();
+        }
+    }
+    // per-bin powers -> LDS (pol 0 writes, pol 1 adds), gathered by the bin table
+    float* P = reinterpret_cast<float*>(s_union);
+#pragma unroll
+    for (int ph = 0; ph < 2; ++ph) {
+        if (pol == ph) {
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                float* rowp = P + (w * 4 + jl[l]) * 512 + 2 * b;
+#pragma unroll
+                for (int d = 0; d < 16; ++d) {
+                    if (ph == 0) {
+                        rowp[32 * d] = acc[l][0][d];
+                        rowp[32 * d + 1] = acc[l][1][d];
+                    } else {
+                        rowp[32 * d] += acc[l][0][d];
+                        rowp[32 * d + 1] += acc[l][1][d];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    write_beams128(P, a.lut + (size_t)row * kBeamNS, a.out + (size_t)wk.unit * kOutPerUnit,
+                   wk.par, t);
+}
+
 }  // namespace
+
+hipError_t launch_fp32_up128(const LaunchArgs& a, hipStream_t stream)
+{
+    if (a.n_units <= 0) return hipSuccess;
+    LaunchArgs args = a;
+    void* params[] = {&args};
+    const void* k = a.sym_ew ? reinterpret_cast<const void*>(&bf_fp32_up128_kernel<true>)
+                             : reinterpret_cast<const void*>(&bf_fp32_up128_kernel<false>);
+    return hipLaunchKernel(k, dev::grid128_for(a.n_units), dim3(dev::kThreads128), params, 0, stream);
+}
 
 hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream)
 {

@@ -361,12 +361,12 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
             const double a = kTwoPi * (double)r / (double)bf::kBins;
             tw[c * 16 + b] = make_float2((float)std::cos(a), (float)-std::sin(a));
         }
-    // w128^(u k) of the 128-point up-channelisation's second pass
-    std::vector<float2> tw128(128);
-    for (int u = 0; u < 8; ++u)
-        for (int k = 0; k < 16; ++k) {
-            const double a = kTwoPi * (double)(u * k) / 128.0;
-            tw128[u * 16 + k] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    // w128^(k m), k < 16, m < 32, of the 128-point up-channelisation
+    std::vector<float2> tw128(16 * 32);
+    for (int k = 0; k < 16; ++k)
+        for (int m = 0; m < 32; ++m) {
+            const double a = kTwoPi * (double)((k * m) % 128) / 128.0;
+            tw128[k * 32 + m] = make_float2((float)std::cos(a), (float)-std::sin(a));
         }
 
     hipError_t e = hipGetDevice(&p->device);
@@ -442,51 +442,25 @@ int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_fram
     if (st != BF_OK || n_frames == 0) return st;
     if (p->cfg.n_time % 128 != 0)
         return fail(p, BF_E_UNSUPPORTED, "the 128-point up-channelisation needs n_time % 128 == 0");
+    bf::LaunchArgs a{};
+    a.in = d_in;
+    a.out = d_out;
+    a.lut = p->d_lut;
+    a.ew = p->d_ew;
+    a.tw = p->d_tw;
+    a.mf = p->d_mf;
+    a.tw128k = p->d_tw128;
+    a.n_chan = p->n_chan;
+    a.n_units = n_frames * p->n_chan;
+    a.n_blk = p->cfg.n_time / bf::kUp;
+    a.n_time = p->cfg.n_time;
+    a.sym_ew = p->sym_ew;
+    a.cyl_sym = p->cyl_sym;
+    a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipSuccess;
-    // whole frames per chunk (so a channel-frame's tables are its row mod
-    // n_chan), about 256 channel-frames of first-pass output at a time
-    const int32_t n_it = p->cfg.n_time / bf::kUp;
-    const size_t per_unit = (size_t)n_it * bf::kFinePerIter * sizeof(float2);  // bytes
-    const int32_t frames_per_chunk = std::max<int32_t>(1, 256 / p->n_chan);
-    const size_t chunk_units = (size_t)frames_per_chunk * p->n_chan;
-    if (p->fine_cap_units < chunk_units) {
-        if (p->d_fine) (void)hipFree(p->d_fine);
-        p->d_fine = nullptr;
-        p->fine_cap_units = 0;
-        if ((e = hipMalloc(&p->d_fine, chunk_units * per_unit)) != hipSuccess)
-            return fail(p, BF_E_NOMEM, std::string("up-channelisation workspace: ") +
-                                           hipGetErrorString(e));
-        p->fine_cap_units = chunk_units;
-    }
-    for (int32_t f0 = 0; f0 < n_frames; f0 += frames_per_chunk) {
-        const int32_t nf = std::min(frames_per_chunk, n_frames - f0);
-        const size_t u0 = (size_t)f0 * p->n_chan;
-        bf::LaunchArgs a{};
-        a.in = d_in + u0 * p->cfg.n_time * bf::kInputs;
-        a.lut = p->d_lut;
-        a.ew = p->d_ew;
-        a.tw = p->d_tw;
-        a.mf = p->d_mf;
-        a.n_chan = p->n_chan;
-        a.n_units = nf * p->n_chan;
-        a.n_blk = n_it;
-        a.n_time = p->cfg.n_time;
-        a.sym_ew = p->sym_ew;
-        a.cyl_sym = p->cyl_sym;
-        a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
-        a.fine = p->d_fine;
-        a.fine_stride8 = 1;
-        e = p->cfg.precision == BF_FP32_FFT ? bf::launch_fp32(a, s) : bf::launch_mfma(a, s);
-        if (e != hipSuccess) return hip_fail(p, e, "first-pass launch");
-        bf::UpchanArgs ua{};
-        ua.fine = p->d_fine;
-        ua.tw128 = p->d_tw128;
-        ua.out = d_out + u0 * bf::kOutPerUnit;
-        ua.n_units = a.n_units;
-        ua.n_blk128 = p->cfg.n_time / 128;
-        if ((e = bf::launch_upchan128(ua, s)) != hipSuccess) return hip_fail(p, e, "second-pass launch");
-    }
+    hipError_t e = p->cfg.precision == BF_FP32_FFT ? bf::launch_fp32_up128(a, s)
+                                                   : bf::launch_mfma_up128(a, s);
+    if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
     return BF_OK;
 }
 
@@ -510,7 +484,6 @@ int32_t beamform_debug_ns(bf_plan* p, const uint8_t* d_in, float* d_ns_out, void
     a.cyl_sym = p->cyl_sym;
     a.split_v = p->cfg.precision == BF_FP32_MFMA ? 1 : 0;
     a.fine = reinterpret_cast<float2*>(d_ns_out);
-    a.fine_stride8 = 0;
     hipError_t e = p->cfg.precision == BF_FP32_FFT ? bf::launch_fp32(a, (hipStream_t)stream)
                                                    : bf::launch_mfma(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
@@ -617,7 +590,6 @@ int32_t beamform_destroy(bf_plan* p)
     if (p->d_ew) (void)hipFree(p->d_ew);
     if (p->d_tw) (void)hipFree(p->d_tw);
     if (p->d_mf) (void)hipFree(p->d_mf);
-    if (p->d_fine) (void)hipFree(p->d_fine);
     if (p->d_tw128) (void)hipFree(p->d_tw128);
     if (p->noalloc_upload) (void)hipEventDestroy(p->noalloc_upload);
     for (bf_plan::EwTrack& t : p->ew_track) {

@@ -32,8 +32,12 @@ struct StreamState {
     int32_t chunk_index;   // chunk of the frame
     int32_t n_chunks;      // chunks per frame
     int32_t n_active;      // active slots; slot[0 .. n_active) are processed
-    int32_t slot[BF_STREAM_MAX_SLOTS];
+    int32_t slot[BF_STREAM_MAX_SLOTS];  // slot index, | kSlotMissing when its frame is missing
 };
+// A slot whose current frame did not arrive complete: its output entry is
+// zeroed (and flagged invalid) instead of beamformed.
+constexpr int32_t kSlotMissing = 1 << 30;
+constexpr int32_t kSlotMask = kSlotMissing - 1;
 constexpr size_t kStreamStateHeader = 4 * sizeof(int32_t);
 
 // Everything a kernel launch needs; device pointers only.
@@ -69,19 +73,15 @@ struct LaunchArgs {
     uint8_t* out_u8;
     const float* scale;
     const float* offset;
-    // Complex beams out (batch mode): instead of integrating power, the kept
-    // beams of every (block iteration it, sub-channel k, line (p, j)) go to
-    // fine[unit][it][k][p * 4 + j][m] (complex FP32).  With fine_stride8 (the
-    // first pass of the 128-point up-channelisation) iteration it takes the 16
-    // samples u + 8 tau of 128-sample block it / 8 (u = it % 8), else 16
-    // consecutive samples (the pre-detection beams).
+    // Complex beams out (batch mode, the pre-detection beams): instead of
+    // integrating power, the kept beams of every (16-sample block it,
+    // sub-channel k, line (p, j)) go to fine[unit][it][k][p * 4 + j][m]
+    // (complex FP32).
     float2* fine;
-    int32_t fine_stride8;
+    // 128-point up-channelisation: tw128k[k * 32 + m] = w128^(k m), k < 16,
+    // m < 32 (FP64 rounded once)
+    const float2* tw128k;
 };
-
-// Complex values per channel-frame in the first pass's output:
-// (n_time / 16 block iterations) x 16 sub-channels x 8 lines x 256 beams.
-constexpr size_t kFinePerIter = 16 * 8 * 256;
 
 // Rows (channel-frames) of the fixed E-W weight table of the allocation-free
 // tracking entry point, and the devices whose copy of it can be addressed.
@@ -93,18 +93,14 @@ hipError_t noalloc_scratch(int device, float2** out);
 
 hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream);
 hipError_t launch_mfma(const LaunchArgs& a, hipStream_t stream);
-
-// Second pass of the 128-point up-channelisation: fine[unit][24][16][8][256]
-// (first-pass output) -> out[unit][1024][16] Stokes I.  tw128[u * 16 + k] =
-// w128^(u k) (FP64 rounded once).
-struct UpchanArgs {
-    const float2* fine;
-    const float2* tw128;
-    float* out;
-    int32_t n_units;
-    int32_t n_blk128;   // 128-sample blocks per frame
-};
-hipError_t launch_upchan128(const UpchanArgs& a, hipStream_t stream);
+// Serving loop, after a frame's last launch: zero the output entries of the
+// active slots marked missing in st and write out_valid (optional,
+// [depth][max_slots]) for every active slot; grid of n_active workgroups.
+hipError_t launch_stream_flags(const StreamState* st, float* out, uint8_t* out_valid, int max_slots,
+                               int n_active, hipStream_t stream);
+// The 128-point up-channelisation in one pass (batch mode, n_time % 128 == 0).
+hipError_t launch_fp32_up128(const LaunchArgs& a, hipStream_t stream);
+hipError_t launch_mfma_up128(const LaunchArgs& a, hipStream_t stream);
 
 // Matrix-core tables of the FP16 path, in per-lane fragment order:
 //   [8][64] x 8 halves  stage-1 DFT-32 block, tile tau in 0..3, hi then lo

@@ -145,11 +145,127 @@ __device__ __forceinline__ void ew_phase(const float2 (&y)[4], const float2 (&W)
     }
 }
 
+// Fixed operands of the four-step transform in this lane's fragment order
+// (stage-1 B tiles, stage-2 A tiles, each as hi + lo; inter-stage twiddles).
+struct NsTables {
+    half8 F1h[4], F1l[4], FDh[2], FDl[2];
+    float2 tw[8];
+};
+__device__ __forceinline__ void load_ns_tables(const void* mf, NsTables& m, int lane)
+{
+    const half8* f1 = reinterpret_cast<const half8*>(mf);
+    const half8* fd = f1 + 8 * 64;
+    const float2* twp = reinterpret_cast<const float2*>(fd + 4 * 64);
+#pragma unroll
+    for (int tau = 0; tau < 4; ++tau) {
+        m.F1h[tau] = f1[(2 * tau) * 64 + lane];
+        m.F1l[tau] = f1[(2 * tau + 1) * 64 + lane];
+    }
+#pragma unroll
+    for (int mu = 0; mu < 2; ++mu) {
+        m.FDh[mu] = fd[(2 * mu) * 64 + lane];
+        m.FDl[mu] = fd[(2 * mu + 1) * 64 + lane];
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) m.tw[e] = twp[lane * 8 + e];
+}
+
+// E-W phasing of one time-DFT slice Ts (float4 per slot = both pols) straight
+// into stage-1 A fragments: lane (q, n) forms feeds 16 a + n, a = 4 q + ia, of
+// the 8 lines (E-W beam j, pol p), rounded once to FP16 (A) or, with kSplitV,
+// as hi + lo (A, Alo).
+template <int kEw, bool kSplitV>
+__device__ __forceinline__ void ew_fragments(const float4* __restrict__ Ts, const float2 (&W)[4][4],
+                                             half8 (&A)[4][2], half8 (&Alo)[4][2], int q, int n)
+{
+    if constexpr (kEw == kEwMirror) {  // both pols per LDS read
+        float2 v[2][4][4];  // [p][j][ia]
+#pragma unroll
+        for (int ia = 0; ia < 4; ++ia) {
+            float2 y0[4], y1[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float4 x4 = Ts[tslot(c * 256 + 16 * (4 * q + ia) + n)];
+                y0[c] = make_float2(x4.x, x4.y);
+                y1[c] = make_float2(x4.z, x4.w);
+            }
+            ew_phase<kEw>(y0, W, v[0], ia);
+            ew_phase<kEw>(y1, W, v[1], ia);
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if constexpr (kSplitV) split_half8(v[p][j], A[j][p], Alo[j][p]);
+                else A[j][p] = pack_half8(v[p][j]);
+            }
+    } else {  // one pol at a time keeps the live set within 2 waves/SIMD
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            float2 v[4][4];  // [j][ia]
+#pragma unroll
+            for (int ia = 0; ia < 4; ++ia) {
+                float2 y[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float4 x4 = Ts[tslot(c * 256 + 16 * (4 * q + ia) + n)];
+                    y[c] = p ? make_float2(x4.z, x4.w) : make_float2(x4.x, x4.y);
+                }
+                ew_phase<kEw>(y, W, v, ia);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if constexpr (kSplitV) split_half8(v[j], A[j][p], Alo[j][p]);
+                else A[j][p] = pack_half8(v[j]);
+            }
+        }
+    }
+}
+
+// N-S transform of one line on the matrix cores, stage 1 and the twiddle:
+// the twiddled stage-1 output as hi + lo B fragments of stage 2.
+template <bool kSplitV>
+__device__ __forceinline__ void ns_stage1(const half8& A, const half8& Alo, const NsTables& m,
+                                          half8 (&Bh)[2], half8 (&Bl)[2])
+{
+    // stage 1: Z = x (rows b) x DFT-32 block, matrix as hi + lo
+    floatx4 D1[4];
+#pragma unroll
+    for (int tau = 0; tau < 4; ++tau) {
+        const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+        D1[tau] = mfma16(A, m.F1h[tau], zero);
+        D1[tau] = mfma16(A, m.F1l[tau], D1[tau]);
+        if constexpr (kSplitV) D1[tau] = mfma16(Alo, m.F1h[tau], D1[tau]);
+    }
+    // twiddle in FP32, split into hi + lo B fragments (K = (b, re/im), column c)
+#pragma unroll
+    for (int nu = 0; nu < 2; ++nu) {
+        float2 z[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            z[i] = cmul(make_float2(D1[nu][i], D1[nu + 2][i]), m.tw[4 * nu + i]);
+        split_half8(z, Bh[nu], Bl[nu]);
+    }
+}
+// Stage 2 for columns c = n + 16 nu: X = DFT-16 block (rows (d, re/im)) x Z';
+// X[mu][i] holds (mu = 0: re, 1: im) of bin n + 16 nu + 32 (4 q + i).
+__device__ __forceinline__ void ns_stage2(const half8& Bh, const half8& Bl, const NsTables& m,
+                                          floatx4 (&X)[2])
+{
+#pragma unroll
+    for (int mu = 0; mu < 2; ++mu) {
+        const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+        X[mu] = mfma16(m.FDh[mu], Bh, zero);
+        X[mu] = mfma16(m.FDl[mu], Bh, X[mu]);
+        X[mu] = mfma16(m.FDh[mu], Bl, X[mu]);
+    }
+}
+
 // kSplitV: also carry the E-W output as hi + lo (stage 1 sums hi*hi + lo*hi +
 // hi*lo): every operand then holds ~22 significant bits and the result is
 // FP32-class (max relative power error ~1e-6 against FP64).
-// kFine: first pass of the 128-point up-channelisation (stride-8 sample
-// blocks; each line's kept beams written out instead of its power summed).
+// kFine: the pre-detection beams (each line's kept beams written out instead
+// of its power summed).
 template <int kEw, bool kSplitV, bool kFine>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bf_mfma_kernel(LaunchArgs a)
@@ -163,24 +279,8 @@ void bf_mfma_kernel(LaunchArgs a)
     const int t = threadIdx.x;
     const int lane = t & 63, s2 = t >> 6, q = lane >> 4, n = lane & 15;
 
-    // fixed matrices in lane order: stage-1 B (4 tiles), stage-2 A (2 tiles), twiddles
-    const half8* f1 = reinterpret_cast<const half8*>(a.mf);
-    const half8* fd = f1 + 8 * 64;
-    const float2* twp = reinterpret_cast<const float2*>(fd + 4 * 64);
-    half8 F1h[4], F1l[4], FDh[2], FDl[2];
-#pragma unroll
-    for (int tau = 0; tau < 4; ++tau) {
-        F1h[tau] = f1[(2 * tau) * 64 + lane];
-        F1l[tau] = f1[(2 * tau + 1) * 64 + lane];
-    }
-#pragma unroll
-    for (int mu = 0; mu < 2; ++mu) {
-        FDh[mu] = fd[(2 * mu) * 64 + lane];
-        FDl[mu] = fd[(2 * mu + 1) * 64 + lane];
-    }
-    float2 tw[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) tw[e] = twp[lane * 8 + e];
+    NsTables mt;
+    load_ns_tables(a.mf, mt, lane);
     float2 W[4][4];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -192,8 +292,7 @@ void bf_mfma_kernel(LaunchArgs a)
 
     const uint8_t* src = io.in;
     uint2 raw[16];
-    const bool s8 = kFine && a.fine_stride8;
-    load_block(block_base(src, 0, s8), raw, t, block_stride(s8));
+    load_block(block_base(src, 0), raw, t);
 
     float acc[4][2][4];  // [E-W beam j][c = n + 16 nu][d = 4 q + i]
     constexpr int kAcc = sizeof(acc) / sizeof(float);
@@ -211,89 +310,23 @@ void bf_mfma_kernel(LaunchArgs a)
     for (int blk = 0; blk < a.n_blk; ++blk) {
         time_dft_class(wk.s0, raw, s_T, t);
         __syncthreads();
-        if (blk + 1 < a.n_blk) load_block(block_base(src, blk + 1, s8), raw, t, block_stride(s8));
+        if (blk + 1 < a.n_blk) load_block(block_base(src, blk + 1), raw, t);
 
-        // E-W phasing straight into stage-1 A fragments: feeds 16 a + n, a = 4q + ia
         half8 A[4][2];
         [[maybe_unused]] half8 Alo[4][2];
-        if constexpr (kEw == kEwMirror) {  // both pols per LDS read
-            float2 v[2][4][4];  // [p][j][ia]
-#pragma unroll
-            for (int ia = 0; ia < 4; ++ia) {
-                float2 y0[4], y1[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const float4 x4 = s_T[s2 * 1024 + tslot(c * 256 + 16 * (4 * q + ia) + n)];
-                    y0[c] = make_float2(x4.x, x4.y);
-                    y1[c] = make_float2(x4.z, x4.w);
-                }
-                ew_phase<kEw>(y0, W, v[0], ia);
-                ew_phase<kEw>(y1, W, v[1], ia);
-            }
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if constexpr (kSplitV) split_half8(v[p][j], A[j][p], Alo[j][p]);
-                    else A[j][p] = pack_half8(v[p][j]);
-                }
-        } else {  // one pol at a time keeps the live set within 2 waves/SIMD
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                float2 v[4][4];  // [j][ia]
-#pragma unroll
-                for (int ia = 0; ia < 4; ++ia) {
-                    float2 y[4];
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const float4 x4 = s_T[s2 * 1024 + tslot(c * 256 + 16 * (4 * q + ia) + n)];
-                        y[c] = p ? make_float2(x4.z, x4.w) : make_float2(x4.x, x4.y);
-                    }
-                    ew_phase<kEw>(y, W, v, ia);
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if constexpr (kSplitV) split_half8(v[j], A[j][p], Alo[j][p]);
-                    else A[j][p] = pack_half8(v[j]);
-                }
-            }
-        }
+        ew_fragments<kEw, kSplitV>(s_T + s2 * 1024, W, A, Alo, q, n);
         __syncthreads();
 
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                // stage 1: Z = x (rows b) x DFT-32 block, matrix as hi + lo
-                floatx4 D1[4];
-#pragma unroll
-                for (int tau = 0; tau < 4; ++tau) {
-                    const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
-                    D1[tau] = mfma16(A[j][p], F1h[tau], zero);
-                    D1[tau] = mfma16(A[j][p], F1l[tau], D1[tau]);
-                    if constexpr (kSplitV) D1[tau] = mfma16(Alo[j][p], F1h[tau], D1[tau]);
-                }
-                // twiddle in FP32, split into hi + lo B fragments (K = (b, re/im), column c)
                 half8 Bh[2], Bl[2];
-#pragma unroll
-                for (int nu = 0; nu < 2; ++nu) {
-                    float2 z[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        z[i] = cmul(make_float2(D1[nu][i], D1[nu + 2][i]), tw[4 * nu + i]);
-                    split_half8(z, Bh[nu], Bl[nu]);
-                }
-                // stage 2: X = DFT-16 block (rows (d, re/im)) x Z'
+                ns_stage1<kSplitV>(A[j][p], kSplitV ? Alo[j][p] : A[j][p], mt, Bh, Bl);
 #pragma unroll
                 for (int nu = 0; nu < 2; ++nu) {
                     floatx4 X[2];
-#pragma unroll
-                    for (int mu = 0; mu < 2; ++mu) {
-                        const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
-                        X[mu] = mfma16(FDh[mu], Bh[nu], zero);
-                        X[mu] = mfma16(FDl[mu], Bh[nu], X[mu]);
-                        X[mu] = mfma16(FDh[mu], Bl[nu], X[mu]);
-                    }
+                    ns_stage2(Bh[nu], Bl[nu], mt, X);
                     if constexpr (kFine) {  // bin n + 16 nu + 32 (4 q + i): (re, im) = (X[0], X[1])
                         float2* bins = s_bins + s2 * 512;
 #pragma unroll
@@ -313,7 +346,7 @@ void bf_mfma_kernel(LaunchArgs a)
                 }
             }
     }
-    if constexpr (kFine) return;  // the second pass detects and integrates
+    if constexpr (kFine) return;  // complex beams only
 
     if (!io.last) {  // frame continues in the next chunk's launch
         store_partial<kAcc>(&acc[0][0][0], io.partial, t);
@@ -332,7 +365,103 @@ void bf_mfma_kernel(LaunchArgs a)
     write_output(P, a, io, wk.s0, t);
 }
 
+// The paper's 128-point up-channelisation in one pass (fine slices and the
+// wave -> sub-channel map: time_dft128 and Work128).  512 threads = 8 waves;
+// per 128-sample block and per bin k of the workgroup's parity, all threads
+// form the 8 fine slices of bin k (128 KB in LDS) and wave w takes the slice
+// whose fine channel lands in its sub-channel through E-W phasing and the
+// matrix-core N-S transform into |X|^2 per bin.
+template <int kEw, bool kSplitV>
+__global__ __launch_bounds__(kThreads128) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void bf_mfma_up128_kernel(LaunchArgs a)
+{
+    __shared__ __align__(16) float4 s_T[8 * 1024];  // 8 fine slices, then per-bin powers
+
+    const Work128 wk = work128_of_block();
+    if (wk.unit >= a.n_units) return;  // uniform across the workgroup
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6, q = lane >> 4, n = lane & 15;
+    const int qw = q128_of_wave(wk.par, w);
+    const int row = wk.unit % a.n_chan;
+
+    NsTables mt;
+    load_ns_tables(a.mf, mt, lane);
+    float2 W[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) W[j][c] = a.ew[((size_t)row * kBeamEW + j) * kCyl + c];
+
+    const __amdgpu_buffer_rsrc_t src = unit_rsrc(a.in + (size_t)wk.unit * a.n_time * kInputs,
+                                                 a.n_time * kInputs);
+    float acc[4][2][4];  // [E-W beam j][c = n + 16 nu][d = 4 q + i]
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int nu = 0; nu < 2; ++nu)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[j][nu][i] = 0.f;
+
+    const int n_blk128 = a.n_time / 128;
+    for (int blk = 0; blk < n_blk128; ++blk) {
+        for (int i = 0; i < 8; ++i) {
+            const int k = k128_of(wk.par, i);
+            time_dft128_bin(k, src, blk * 128 * kInputs, a.tw128k + k * 32, s_T, t);
+            __syncthreads();
+            half8 A[4][2];
+            [[maybe_unused]] half8 Alo[4][2];
+            ew_fragments<kEw, kSplitV>(s_T + r128_for(k, qw) * 1024, W, A, Alo, q, n);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    half8 Bh[2], Bl[2];
+                    ns_stage1<kSplitV>(A[j][p], kSplitV ? Alo[j][p] : A[j][p], mt, Bh, Bl);
+#pragma unroll
+                    for (int nu = 0; nu < 2; ++nu) {
+                        floatx4 X[2];
+                        ns_stage2(Bh[nu], Bl[nu], mt, X);
+#pragma unroll
+                        for (int ii = 0; ii < 4; ++ii)
+                            acc[j][nu][ii] = fmaf(X[0][ii], X[0][ii], fmaf(X[1][ii], X[1][ii], acc[j][nu][ii]));
+                    }
+                }
+        }
+    }
+    // per-bin powers -> LDS (bin c + 32 d of wave w, E-W beam j), then gather
+    float* P = reinterpret_cast<float*>(s_T);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int nu = 0; nu < 2; ++nu)
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii)
+                P[(w * 4 + j) * 512 + n + 16 * nu + 32 * (4 * q + ii)] = acc[j][nu][ii];
+    __syncthreads();
+    write_beams128(P, a.lut + (size_t)row * kBeamNS, a.out + (size_t)wk.unit * kOutPerUnit,
+                   wk.par, t);
+}
+
 }  // namespace
+
+hipError_t launch_mfma_up128(const LaunchArgs& a, hipStream_t stream)
+{
+    if (a.n_units <= 0) return hipSuccess;
+    LaunchArgs args = a;
+    void* params[] = {&args};
+    // [E-W form][split]
+    static const void* const kKernels[3][2] = {
+        {reinterpret_cast<const void*>(&bf_mfma_up128_kernel<kEwGeneral, false>),
+         reinterpret_cast<const void*>(&bf_mfma_up128_kernel<kEwGeneral, true>)},
+        {reinterpret_cast<const void*>(&bf_mfma_up128_kernel<kEwCyl, false>),
+         reinterpret_cast<const void*>(&bf_mfma_up128_kernel<kEwCyl, true>)},
+        {reinterpret_cast<const void*>(&bf_mfma_up128_kernel<kEwMirror, false>),
+         reinterpret_cast<const void*>(&bf_mfma_up128_kernel<kEwMirror, true>)}};
+    const int ew = a.sym_ew ? kEwMirror : a.cyl_sym ? kEwCyl : kEwGeneral;
+    return hipLaunchKernel(kKernels[ew][a.split_v ? 1 : 0], dev::grid128_for(a.n_units),
+                           dim3(dev::kThreads128), params, 0, stream);
+}
 
 hipError_t launch_mfma(const LaunchArgs& a, hipStream_t stream)
 {

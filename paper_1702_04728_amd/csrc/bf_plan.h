@@ -31,10 +31,7 @@ struct bf_plan {
         hipEvent_t done = nullptr;
     } ew_track[2];
     int ew_track_next = 0;
-    // 128-point up-channelisation: first-pass workspace (capacity in
-    // channel-frames) and the w128^(u k) table
-    float2* d_fine = nullptr;
-    size_t fine_cap_units = 0;
+    // 128-point up-channelisation: the w128^(k m) table
     float2* d_tw128 = nullptr;
     // Allocation-free tracking: this device's fixed weight table (library-wide,
     // not owned by the plan) and the event that tells when its upload has read

@@ -33,14 +33,23 @@ constexpr size_t kTabBytes = bf::kBeamNS * sizeof(int32_t) + bf::kBeamEW * bf::k
 // Channel slots, admission and event application (pure host; no device).
 struct Scheduler {
     int max_slots, capacity;
+    bf_config geo;  // geometry and pointings a joining channel's Eq. (1) bins use
     std::vector<int32_t> slot_chan;
     std::vector<double> slot_freq;
     int n_active = 0;
     int64_t joins = 0, leaves = 0, rejected = 0, ignored = 0;
 
-    Scheduler(int max_slots_, int capacity_)
-        : max_slots(max_slots_), capacity(capacity_), slot_chan(max_slots_, -1),
+    Scheduler(int max_slots_, int capacity_, const bf_config& geo_)
+        : max_slots(max_slots_), capacity(capacity_), geo(geo_), slot_chan(max_slots_, -1),
           slot_freq(max_slots_, 0.0) {}
+
+    // The channel's Eq. (1) bin table can be formed (finite, positive frequency
+    // whose argument stays within an exact integer floor).
+    bool freq_ok(double f)
+    {
+        int32_t bins[bf::kBeamNS];
+        return std::isfinite(f) && f > 0.0 && beamform_compute_lut(&geo, &f, 1, bins) == BF_OK;
+    }
 
     int find(int32_t chan) const
     {
@@ -52,8 +61,7 @@ struct Scheduler {
     int apply(const bf_stream_event& e)
     {
         if (e.op == BF_STREAM_JOIN) {
-            if (e.channel_id < 0 || find(e.channel_id) >= 0 || !(e.freq_hz > 0.0) ||
-                !std::isfinite(e.freq_hz)) {
+            if (e.channel_id < 0 || find(e.channel_id) >= 0 || !freq_ok(e.freq_hz)) {
                 ++ignored;
                 return -1;
             }
@@ -119,11 +127,34 @@ int32_t check_desc(const bf_stream_desc* d, std::string* msg)
     return BF_OK;
 }
 
-int64_t per_slot_bytes(int depth, int n_time)
+int64_t per_slot_bytes(int depth, int n_time, bool partial_sums)
 {
-    // the slot's share of both rings, its partial sums and its table rows
+    // the slot's share of both rings, its partial sums (chunked ingest only) and
+    // its table rows
     return (int64_t)depth * ((int64_t)n_time * bf::kInputs + (int64_t)bf::kOutPerUnit * 4) +
-           (int64_t)4 * bf::kPartialPerWg * 4 + (int64_t)kTabBytes;
+           (partial_sums ? (int64_t)4 * bf::kPartialPerWg * 4 : 0) + (int64_t)kTabBytes;
+}
+
+// Default geometry for the host-only dry run's Eq. (1) check.
+bf_config default_geometry()
+{
+    bf_config c;
+    beamform_default_config(&c);
+    return c;
+}
+
+// Active slots of frame i for the launches: the slot indices, each marked
+// missing when the ingest did not deliver that channel-frame.  Returns the
+// number of missing ones.
+int mark_missing(const bf_stream_desc* d, int32_t i, const int32_t* act, int n_act, int32_t* out)
+{
+    int missing = 0;
+    for (int u = 0; u < n_act; ++u) {
+        const bool ok = !d->ingest_ok || d->ingest_ok[(size_t)i * d->max_slots + act[u]] != 0;
+        out[u] = ok ? act[u] : (act[u] | bf::kSlotMissing);
+        missing += ok ? 0 : 1;
+    }
+    return missing;
 }
 
 double quantile(std::vector<double> v, double q)
@@ -136,21 +167,24 @@ double quantile(std::vector<double> v, double q)
     return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
 }
 
-// Bin table and E-W weights of one channel (FP64, rounded once), as in beamform_init.
-void channel_tables(const bf_plan* p, double f, unsigned char* dst)
+// Bin table and E-W weights of one channel (FP64, rounded once), as in
+// beamform_init; false if the bin table cannot be formed (the scheduler admits
+// no such channel).
+bool channel_tables(const bf_plan* p, double f, unsigned char* dst)
 {
     int32_t* lut = reinterpret_cast<int32_t*>(dst);
     float2* ew = reinterpret_cast<float2*>(dst + bf::kBeamNS * sizeof(int32_t));
     bf_config c = p->cfg;
     c.sin_theta_ns = p->sin_theta.data();
     c.lut_override = nullptr;
-    (void)beamform_compute_lut(&c, &f, 1, lut);
+    if (beamform_compute_lut(&c, &f, 1, lut) != BF_OK) return false;
     const double two_pi = 6.283185307179586476925286766559;
     for (int j = 0; j < bf::kBeamEW; ++j)
         for (int cy = 0; cy < bf::kCyl; ++cy) {
             const double a = two_pi * f * p->cyl_x[cy] * p->sin_phi[j] / p->cfg.c0;
             ew[j * bf::kCyl + cy] = make_float2((float)std::cos(a), (float)-std::sin(a));
         }
+    return true;
 }
 
 struct LaunchRec {
@@ -170,7 +204,8 @@ int32_t beamform_stream_schedule(const bf_stream_desc* d, int64_t psb, int64_t c
     if (check_desc(d, &msg) != BF_OK || psb <= 0 || cap < 0 || !st) return BF_E_INVAL;
     std::memset(st, 0, sizeof(*st));
     const int capacity = (int)std::min<int64_t>(d->max_slots, cap / psb);
-    Scheduler sch(d->max_slots, capacity);
+    Scheduler sch(d->max_slots, capacity, default_geometry());
+    std::vector<int32_t> act(d->max_slots), marked(d->max_slots);
     int32_t ev = 0;
     st->min_active = d->n_frames > 0 ? d->max_slots : 0;
     for (int32_t i = 0; i < d->n_frames; ++i) {
@@ -178,6 +213,8 @@ int32_t beamform_stream_schedule(const bf_stream_desc* d, int64_t psb, int64_t c
         if (d->slot_log)
             std::memcpy(d->slot_log + (size_t)i * d->max_slots, sch.slot_chan.data(),
                         sizeof(int32_t) * d->max_slots);
+        const int n_act = sch.active(act.data());
+        st->missing_frames += mark_missing(d, i, act.data(), n_act, marked.data());
         st->channel_frames += sch.n_active;
         st->max_active = std::max(st->max_active, sch.n_active);
         st->min_active = std::min(st->min_active, sch.n_active);
@@ -220,7 +257,7 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     }
     const int n_chunks = n_time / chunk;
     std::memset(st, 0, sizeof(*st));
-    const int64_t psb = per_slot_bytes(d->depth, n_time);
+    const int64_t psb = per_slot_bytes(d->depth, n_time, n_chunks > 1);
     int64_t cap = d->mem_cap_bytes;
     if (cap == 0) {
         size_t free_b = 0, total_b = 0;
@@ -364,9 +401,12 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     };
 
     // ---- main loop ----
-    Scheduler sch(S, capacity);
+    bf_config geo = p->cfg;
+    geo.sin_theta_ns = p->sin_theta.data();
+    geo.lut_override = nullptr;
+    Scheduler sch(S, capacity, geo);
     std::vector<int64_t> tab_launch(S, -1);
-    std::vector<int32_t> act(S);
+    std::vector<int32_t> act(S), act_launch(S);
     int32_t evi = 0;
     int64_t L = 0;
     st->min_active = d->n_frames > 0 ? S : 0;
@@ -388,7 +428,11 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
                 }
             }
             unsigned char* row = h_tab + kTabBytes * slot;
-            channel_tables(p, sch.slot_freq[slot], row);
+            if (!channel_tables(p, sch.slot_freq[slot], row)) {
+                status = BF_E_STATE;
+                e = hipErrorInvalidValue;
+                break;
+            }
             if ((e = hipMemcpyAsync(d_lut + (size_t)slot * bf::kBeamNS, row,
                                     bf::kBeamNS * sizeof(int32_t), hipMemcpyHostToDevice, s)) != hipSuccess ||
                 (e = hipMemcpyAsync(d_ew + (size_t)slot * bf::kBeamEW * bf::kCyl,
@@ -404,6 +448,8 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
         const int n_act = sch.active(act.data());
         if (d->slot_log)
             std::memcpy(d->slot_log + (size_t)i * S, sch.slot_chan.data(), sizeof(int32_t) * S);
+        const int n_missing = mark_missing(d, i, act.data(), n_act, act_launch.data());
+        st->missing_frames += n_missing;
         st->channel_frames += n_act;
         st->max_active = std::max(st->max_active, n_act);
         st->min_active = std::min(st->min_active, n_act);
@@ -430,12 +476,15 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
             hs.chunk_index = c;
             hs.n_chunks = n_chunks;
             hs.n_active = n_act;
-            std::memcpy(hs.slot, act.data(), sizeof(int32_t) * n_act);
+            std::memcpy(hs.slot, act_launch.data(), sizeof(int32_t) * n_act);
             recs[k] = LaunchRec{i, c == n_chunks - 1, avail};
             if ((e = hipMemcpyAsync(d_state, &hs, bf::kStreamStateHeader + sizeof(int32_t) * n_act,
                                     hipMemcpyHostToDevice, s)) != hipSuccess ||
                 (e = hipEventRecord(ev_start[k], s)) != hipSuccess ||
                 (e = (d->use_graph ? hipGraphLaunch(exec, s) : launch(s))) != hipSuccess ||
+                (c == n_chunks - 1 && (n_missing > 0 || d->d_out_valid) &&
+                 (e = bf::launch_stream_flags(d_state, d->d_out_ring, d->d_out_valid, S, n_act, s)) !=
+                     hipSuccess) ||
                 (e = hipEventRecord(ev_end[k], s)) != hipSuccess) {
                 status = BF_E_DEVICE;
                 break;
@@ -463,6 +512,8 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     st->leaves = sch.leaves;
     st->rejected_joins = sch.rejected;
     st->ignored_events = sch.ignored + (d->n_events - evi);
+    if (d->latency_log_ms && !lat_ms.empty())
+        std::memcpy(d->latency_log_ms, lat_ms.data(), sizeof(double) * lat_ms.size());
     // latency and service statistics over the frames after the warm-up
     lat_ms.erase(lat_ms.begin(), lat_ms.begin() + d->warmup_frames);
     svc_ms.erase(svc_ms.begin(), svc_ms.begin() + d->warmup_frames);

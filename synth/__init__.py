@@ -220,19 +220,22 @@ JOIN, LEAVE = 1, 2
 
 
 def churn_events(seed: int, n_frames: int, n_ids: int = 1024, initial: int = 64,
-                 rate_join: float = 0.02, rate_leave: float = 0.02, lo: int = 16, hi: int = 128):
+                 rate_join=0.02, rate_leave=0.02, lo: int = 16, hi: int = 128):
     """Seeded channel churn for the serving loop: frame 0 joins `initial` channel ids drawn
     from [0, n_ids); then per frame Poisson(rate_join) joins and Poisson(rate_leave) leaves,
     ids drawn uniformly from the inactive / active sets.  Events that would take the active
-    count outside [lo, hi] are counted in `clamped` and not emitted.
+    count outside [lo, hi] are counted in `clamped` and not emitted.  Each rate is a number
+    or a per-frame sequence of length n_frames.
     Returns (events [(frame, op, id, freq_hz)], clamped)."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    rj = np.broadcast_to(np.asarray(rate_join, dtype=np.float64), (n_frames,))
+    rl = np.broadcast_to(np.asarray(rate_leave, dtype=np.float64), (n_frames,))
     active = set(int(c) for c in rng.choice(n_ids, size=initial, replace=False))
     events = [(0, JOIN, c, float(chan_freq_hz(c))) for c in sorted(active)]
     clamped = 0
     for f in range(1, n_frames):
-        nj = int(rng.poisson(rate_join))
-        nl = int(rng.poisson(rate_leave))
+        nj = int(rng.poisson(rj[f]))
+        nl = int(rng.poisson(rl[f]))
         for _ in range(nl):
             if len(active) <= lo:
                 clamped += 1
@@ -249,6 +252,16 @@ def churn_events(seed: int, n_frames: int, n_ids: int = 1024, initial: int = 64,
             active.add(c)
             events.append((f, JOIN, c, float(chan_freq_hz(c))))
     return events, clamped
+
+
+def churn_rates_to_clamps(n_frames: int, fast: float = 0.05, slow: float = 0.01):
+    """Per-frame (join, leave) Poisson rates that drive the active count up, then
+    down, then up again (net +-0.04 channels per frame over quarters, a half and a
+    quarter of the run), so that a serving run from 120 channels reaches both the
+    128-channel and the 16-channel clamp."""
+    f = np.arange(n_frames)
+    down = (f >= n_frames // 4) & (f < 3 * n_frames // 4)
+    return np.where(down, slow, fast), np.where(down, fast, slow)
 
 
 def frame_pool(seed: int, n_distinct: int, sigma: float = SIGMA, freq_hz: float = 600e6,

@@ -97,7 +97,7 @@ def test_u8_full_size(torch_mod, bfm, oracle_mod, workload, precision):
 
 @pytest.mark.parametrize("precision", PRECISIONS)
 def test_upchan128_full_size_sampled(torch_mod, bfm, oracle_mod, workload, precision):
-    """Two workspace chunks of 64 frames each, as the bench runs them."""
+    """The bench's one-launch 128-point step at full size, sampled against the oracle."""
     raw, freqs, d = workload
     print("upchan128 full size %s" % precision, flush=True)
     with bfm.Beamformer(freqs, precision=precision) as b:

@@ -180,3 +180,39 @@ def test_stream_argument_errors(torch_mod, bfm, pool):
         st, _ = b.stream(ring, out, [(0, J, 1, 5e8)], 5, warmup_frames=5)
         assert st["frames"] == 5 and st["channel_frames"] == 5 and st["late_frames"] == 0
         assert st["latency_p99_ms"] == 0.0
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp32_mfma"])
+@pytest.mark.parametrize("chunk", [0, 128])
+def test_lossy_ingest_zeroes_and_flags_missing_frames(torch_mod, bfm, pool, precision, chunk):
+    """Channel-frames the ingest did not deliver (ingest_ok = 0: an empty or late
+    ring entry) are skipped: their output entry is exactly zero and flagged 0 in
+    out_valid, and they are counted; every delivered one is flagged 1 and equals
+    the batch path bit for bit, also right after a loss with chunked ingest (the
+    partial sums restart at each frame's first chunk)."""
+    ring = _ring(torch_mod, pool, 4, 6)
+    rng = np.random.default_rng(11)
+    ok = (rng.random((10, 6)) > 0.3).astype(np.uint8)
+    depth, slots = 4, 6
+    valid = torch_mod.full((depth, slots), 255, dtype=torch_mod.uint8, device="cuda")
+    st, log, out = _stream(torch_mod, bfm, ring, precision, chunk=chunk, ingest_ok=ok,
+                           out_valid=valid)
+    valid = valid.cpu().numpy()
+    assert st["missing_frames"] == int(((log >= 0) & (ok == 0)).sum()) > 0
+    ring_np = ring.cpu().numpy()
+    n_missing = n_ok = 0
+    for i in range(6, 10):                       # the ring keeps the last 4 frames
+        for s in range(slots):
+            if log[i][s] < 0:
+                continue
+            if not ok[i][s]:
+                assert valid[i % 4, s] == 0
+                assert not out[i % 4, s].any()
+                n_missing += 1
+                continue
+            assert valid[i % 4, s] == 1
+            with bfm.Beamformer([_f(int(log[i][s]))], precision=precision) as b:
+                ref = b.frame(torch_mod.from_numpy(ring_np[i % 4, s][None, None]).cuda())
+            np.testing.assert_array_equal(out[i % 4, s], ref.cpu().numpy()[0, 0])
+            n_ok += 1
+    assert n_missing >= 2 and n_ok >= 6

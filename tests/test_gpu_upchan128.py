@@ -2,7 +2,7 @@
 Sec. 3 and Sec. 3.2), all three precisions: per-output parity with the oracle (128-point DFTs of
 128-sample blocks, fine bins grouped 8 to a sub-channel), the closed-form
 relations to the 16-point path (a channel-centre tone: same sub-channel, 8 times
-the power; any input: 8 times the total power), several workspace chunks, and
+the power; any input: 8 times the total power), large and split batches, and
 the unsupported configurations."""
 import numpy as np
 import pytest
@@ -80,9 +80,9 @@ def test_general_geometry_parity(torch_mod, bfm, oracle_mod, precision, cyl_x):
     assert err.max() <= TOLS[precision]
 
 
-def test_many_chunks_sampled(torch_mod, bfm, oracle_mod):
-    """300 channels: one frame per workspace chunk, 3 chunks; seeded channel-frames
-    against the oracle."""
+def test_many_channels_sampled(torch_mod, bfm, oracle_mod):
+    """300 channels x 3 frames in one call; seeded channel-frames against the
+    oracle."""
     n_frames, n_chan = 3, 300
     raw = synth.noise_frames(43, 1, 1)
     raw = np.ascontiguousarray(np.broadcast_to(raw, (n_frames, n_chan, 384, 2048)))
@@ -96,11 +96,10 @@ def test_many_chunks_sampled(torch_mod, bfm, oracle_mod):
         assert err.max() <= TOL, (f, c, err.max())
 
 
-def test_uneven_chunks_match_one_chunk(torch_mod, bfm, oracle_mod):
-    """4 channels x 66 frames: workspace chunks of 64 and 2 frames, the second
-    reusing the first's workspace.  Frames 62-65 (both sides of the chunk boundary)
-    equal, bit for bit, the same frames beamformed in one call of their own (one
-    chunk), and two of them match the oracle."""
+def test_batch_split_matches_one_call(torch_mod, bfm, oracle_mod):
+    """4 channels x 66 frames: frames 62-65 of one call equal, bit for bit, the
+    same frames beamformed in a call of their own (each channel-frame is
+    independent of the batch around it), and two of them match the oracle."""
     n_frames, n_chan = 66, 4
     raw = synth.uniform_bytes(46, (n_frames, n_chan, 384, 2048))
     freqs = synth.chan_freq_hz([100, 400, 700, 1000])
@@ -135,9 +134,8 @@ def test_closed_form_relations_to_16_point(torch_mod, bfm):
 def test_full_scale_coherent_input(torch_mod, bfm, oracle_mod, precision):
     """Every input at the most negative code (-8 - 8i) in every sample: the largest
     beams any frame can produce (N-S bin 0 of a coherent line, about 2^17.5 in
-    amplitude before detection), all in the channel-centre sub-channel, pass through
-    the workspace between the two passes intact; the other sub-channels stay at
-    rounding level."""
+    amplitude before detection), all in the channel-centre sub-channel, stay exact
+    to the path's tolerance; the other sub-channels stay at rounding level."""
     raw = np.zeros((1, 2, 384, 2048), np.uint8)
     freqs = synth.chan_freq_hz([20, 1000])
     got = _run(torch_mod, bfm, raw, freqs, 128, precision=precision)
@@ -155,9 +153,9 @@ def test_full_scale_coherent_input(torch_mod, bfm, oracle_mod, precision):
 def test_config4_sky_parity(torch_mod, bfm, oracle_mod, precision):
     """Config-4 inputs (noise, DM-500 pulse, RFI tones identical on every input) in the
     128-point form: a strong tone concentrates into one fine channel, and any rounding
-    of the beams between the two passes leaks into the noise-only fine channels of
-    the neighbouring sub-channels (FP16-rounded intermediate beams reached 2.3e-3
-    here; FP32 ones keep the path at its own precision)."""
+    applied before the 8-point DFT over sample phases would leak it into the
+    noise-only fine channels of the neighbouring sub-channels (FP16-rounded
+    intermediate beams of an earlier two-pass form reached 2.3e-3 here)."""
     c_idx = synth.sweep_c_idx(64)[[20, 31, 50]]
     raw = synth.config4_frames(1004, c_idx, [0], sky=synth.config4_sky(1004, c_idx))
     freqs = synth.chan_freq_hz(c_idx)

@@ -125,3 +125,34 @@ def test_schedule_rejects_bad_descriptors():
             bf.stream_schedule([], 5, 4, PSB, 4 * PSB, warmup_frames=bad)
     for ok in (0, 5):
         bf.stream_schedule([], 5, 4, PSB, 4 * PSB, warmup_frames=ok)
+
+
+def test_join_with_unformable_bin_table_is_ignored():
+    """A JOIN whose Eq. (1) bins cannot be formed (frequency so large that the
+    argument leaves the exact integer floor, or not finite) is ignored, as a bad
+    frequency is, instead of admitting a slot with a stale bin table."""
+    ev = [(0, J, 1, 600e6), (0, J, 2, 1e30), (0, J, 3, float("inf")), (0, J, 4, float("nan")),
+          (1, J, 5, 700e6)]
+    st, log = bf.stream_schedule(ev, 3, 8, PSB, 8 * PSB)
+    assert log[0].tolist()[:2] == [1, -1]
+    assert log[2].tolist()[:3] == [1, 5, -1]
+    assert (st["joins"], st["ignored_events"]) == (2, 3)
+
+
+def test_missing_frames_counted_for_active_slots_only():
+    """Lossy ingest: a zero in ingest_ok marks a channel-frame that did not arrive.
+    The dry run counts exactly the zeros that fall on active slots (an empty slot
+    has no frame to lose), every frame and warm-up included."""
+    rng = np.random.default_rng(5)
+    ev, _ = synth.churn_events(9, 40, n_ids=64, initial=5, rate_join=0.3, rate_leave=0.3,
+                               lo=2, hi=7)
+    ok = (rng.random((40, 8)) > 0.25).astype(np.uint8)
+    st, log = bf.stream_schedule(ev, 40, 8, PSB, 8 * PSB, warmup_frames=5, ingest_ok=ok)
+    expect = int(((log >= 0) & (ok == 0)).sum())
+    assert expect > 10
+    assert st["missing_frames"] == expect
+    st0, log0 = bf.stream_schedule(ev, 40, 8, PSB, 8 * PSB)
+    assert st0["missing_frames"] == 0
+    np.testing.assert_array_equal(log, log0)   # losses never change the schedule
+    with pytest.raises(ValueError):
+        bf.stream_schedule(ev, 40, 8, PSB, 8 * PSB, ingest_ok=ok[:, :4])
