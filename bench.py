@@ -129,21 +129,22 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def device_warmup(torch, seconds: float) -> int:
-    """Untimed device copies for about `seconds`, before anything is timed: a
-    fresh process starts the GPU below its sustained clock, and a real-time
-    beamformer runs at the sustained one.  Returns the copies issued."""
-    n = 256 << 20
-    src = torch.ones(n, dtype=torch.uint8, device="cuda")
-    dst = torch.empty_like(src)
+def device_warmup(torch, bf, prec, raw, freqs, seconds: float) -> int:
+    """Untimed beamforming launches for about `seconds` before anything is timed:
+    a fresh process starts the GPU below its sustained clock (the first path's
+    timing ran 5-6 % slow without this), and a real-time beamformer runs at the
+    sustained one.  Returns the launches issued."""
+    beam = bf.Beamformer(freqs, precision=prec)
+    out = torch.empty(beam.out_shape(raw.shape[0]), dtype=torch.float32, device=raw.device)
     t0 = time.perf_counter()
     k = 0
     while time.perf_counter() - t0 < seconds:
-        for _ in range(20):
-            dst.copy_(src)
+        for _ in range(10):
+            beam.frame(raw, out)
         torch.cuda.synchronize()
-        k += 20
-    del src, dst
+        k += 10
+    beam.close()
+    del out
     return k
 
 
@@ -395,11 +396,11 @@ def main():
                     help="frames at the start of each sweep point left out of its statistics")
     ap.add_argument("--sweep-chunk", type=int, default=0,
                     help="samples per serving-loop launch in the sweep (0: whole frames)")
-    ap.add_argument("--sweep-list", default="512,576,640,704",
+    ap.add_argument("--sweep-list", default="512,576,640,704,768",
                     help="channel counts of the paced sweep, ascending (the full sweep: "
                          "64,128,192,256,320,384,448,512,544,576,608,640,704,768)")
-    ap.add_argument("--warmup-seconds", type=float, default=1.5,
-                    help="untimed device copies before the first timed launch")
+    ap.add_argument("--warmup-seconds", type=float, default=2.0,
+                    help="seconds of untimed launches of the first path before any timing")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -427,9 +428,10 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     raw = torch.from_numpy(raw_np).to(dev)
-    if args.warmup_seconds > 0:
-        log("device warm-up: %d untimed 256 MiB copies" % device_warmup(torch, args.warmup_seconds))
     paths = ["fp32", "fp16", "fp32_mfma"] if args.precision == "all" else [args.precision]
+    if args.warmup_seconds > 0:
+        log("device warm-up: %d untimed launches" % device_warmup(torch, bf, paths[0], raw, freqs,
+                                                                  args.warmup_seconds))
     results = {}
     for prec in paths:
         results[prec] = time_path(torch, bf, prec, raw, freqs, units, args)

@@ -120,14 +120,15 @@ class Geometry:
 _lib = None
 
 
-def build_variant(src_text: str, out_path: str) -> str:
+def build_variant(src_text: str, out_path: str, extra_flags=()) -> str:
     """Compile another oracle source (e.g. a deliberately broken copy used to check
-    that the pins detect mistakes) into out_path."""
+    that the pins detect mistakes, or the oracle itself with sanitizer flags) into
+    out_path."""
     src = out_path + ".c"
     with open(src, "w") as f:
         f.write(src_text)
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o",
-                           out_path, src, "-lm"])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared"]
+                          + list(extra_flags) + ["-o", out_path, src, "-lm"])
     return out_path
 
 
@@ -149,9 +150,12 @@ class use_library:
 
 
 def _load():
+    """The oracle library: liboracle.so, or the build named by ORACLE_LIB (a
+    sanitizer build of the same source, for the CPU hygiene runs)."""
     global _lib
     if _lib is None:
-        _lib = _bind(ctypes.CDLL(build()))
+        alt = os.environ.get("ORACLE_LIB")
+        _lib = _bind(ctypes.CDLL(alt if alt else build()))
     return _lib
 
 

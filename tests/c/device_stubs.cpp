@@ -1,0 +1,23 @@
+// Stand-ins for the library's device-side launchers, so that its host-only code
+// (bf_host.cpp, bf_stream.cpp) links into a program without device code: the
+// sanitizer build of the C ABI harness, which calls only host-only entry points.
+// Each returns an error; none is reached by that harness.
+#include <hip/hip_runtime.h>
+
+#include "../../paper_1702_04728_amd/csrc/bf_internal.h"
+
+namespace bf {
+hipError_t launch_fp32(const LaunchArgs&, hipStream_t) { return hipErrorNoBinaryForGpu; }
+hipError_t launch_mfma(const LaunchArgs&, hipStream_t) { return hipErrorNoBinaryForGpu; }
+hipError_t launch_fp32_up128(const LaunchArgs&, hipStream_t) { return hipErrorNoBinaryForGpu; }
+hipError_t launch_mfma_up128(const LaunchArgs&, hipStream_t) { return hipErrorNoBinaryForGpu; }
+hipError_t launch_stream_flags(const StreamState*, float*, uint8_t*, int, int, hipStream_t)
+{
+    return hipErrorNoBinaryForGpu;
+}
+hipError_t noalloc_scratch(int, float2** out)
+{
+    *out = nullptr;
+    return hipErrorNoBinaryForGpu;
+}
+}  // namespace bf

@@ -156,3 +156,83 @@ def test_beam_width_at_band_bottom(torch_mod, bfm, m, span, paper_deg, paper_zen
     # scaled to the paper's elevation, the width is the paper's figure
     w_paper = w * math.cos(math.radians(centre)) / math.cos(math.radians(paper_zenith_deg))
     assert w_paper == pytest.approx(paper_deg, rel=0.1)
+
+
+def _ew_af(f, u):
+    """Closed-form power response of the 4 static E-W beams (R7 pointings, cylinders
+    20 m apart) to a plane wave at E-W direction cosine u, per channel frequency f:
+    [n_f][4]."""
+    x = (np.arange(4) - 1.5) * 20.0
+    sphi = np.sin(np.deg2rad((np.arange(4) - 1.5) * 0.4))
+    ph = 2j * np.pi * np.asarray(f)[:, None, None] * x[None, None, :] \
+        * (u - sphi)[None, :, None] / C0
+    return np.abs(np.exp(ph).sum(axis=2)) ** 2
+
+
+def _eq1_bins(f):
+    """Eq. (1) for every channel and pointing, restated in FP64: [n_f][256]."""
+    arg = 512 * np.asarray(f)[:, None] * D * SIN_M[None, :] / C0 + 0.5
+    return np.mod(np.floor(arg).astype(np.int64), 512)
+
+
+@pytest.fixture(scope="module", params=["fp32", "fp16"])
+def summed_map(request, torch_mod, bfm):
+    """Fig. 3's frequency-summed response: one noiseless frame of all 1024 channels
+    with a source at 26 deg N-S, 0.2 deg E-W (on E-W beam 2), every output summed
+    over the 16 sub-channels and the 1024 channels per beam."""
+    precision = request.param
+    raw = synth.point_source_frames(F_ALL, S26, phi_deg=0.2)
+    print("summed map: 1024 channels x 1 frame, %s" % precision, flush=True)
+    with bfm.Beamformer(F_ALL, precision=precision) as b:
+        out = b.frame(torch_mod.from_numpy(raw).cuda())
+        torch_mod.cuda.synchronize()
+        out = out.cpu().numpy()[0].astype(np.float64)
+    return precision, raw, out
+
+
+def test_frequency_summed_map(summed_map, oracle_mod):
+    """The summed map (Sec. 3.3, Fig. 3) against the closed-form array factors summed
+    over the same channels: M[j][m] = sum_f AF_EW(j, f) AF_NS(k_m(f), f), independent
+    of the oracle.  It peaks at the source's N-S pointing in its E-W beam; the alias
+    south of zenith (from about 684 MHz up) is smeared over the pointings Sec. 3.3
+    shows (about -88 .. -50 deg), much weaker than the main beam, with the summed
+    alias-to-main ratio the closed form predicts; sampled channels match the oracle."""
+    precision, raw, out = summed_map
+    m_map = out.sum(axis=(0, 2)).reshape(4, 256)
+    v = math.cos(math.radians(0.2)) * S26
+    kappa = 512 * F_ALL * D * v / C0
+    bins = _eq1_bins(F_ALL)
+    n = np.arange(256)
+    af_ns = np.abs(np.exp(2j * np.pi * (kappa[:, None, None] - bins[:, :, None]) * n / 512)
+                   .sum(axis=2)) ** 2                                  # [f][m]
+    af_ew = _ew_af(F_ALL, math.sin(math.radians(0.2)))                  # [f][j]
+    pred = np.einsum("fj,fm->jm", af_ew, af_ns)
+    j0, m0 = np.unravel_index(np.argmax(m_map), m_map.shape)
+    jp, mp = np.unravel_index(np.argmax(pred), pred.shape)
+    print("summed map %s: peak beam (j %d, m %d) at %.2f deg; closed form (j %d, m %d)"
+          % (precision, j0, m0, math.degrees(math.asin(SIN_M[m0])), jp, mp))
+    assert (j0, m0) == (jp, mp) == (2, int(np.argmin(np.abs(SIN_M - S26))))
+    # whole map: shape of the closed form within the 4-bit tone's spatial harmonics
+    mm, pp = m_map / m_map.max(), pred / pred.max()
+    assert np.abs(mm - pp).max() <= 0.005
+    south = SIN_M < 0
+    row, row_p = mm[j0], pp[j0]
+    ratio, ratio_p = row[south].max(), row_p[south].max()
+    print("summed alias / main: gpu %.4f, closed form %.4f" % (ratio, ratio_p))
+    assert ratio < 0.25                      # much weaker than the main beam
+    assert abs(ratio - ratio_p) <= 0.05 * ratio_p + 0.001
+    # where the alias power lies: pointings holding at least a tenth of the alias peak
+    smear = np.degrees(np.arcsin(SIN_M[south & (row >= 0.1 * ratio)]))
+    print("alias smear: %.2f .. %.2f deg over %d pointings" % (smear.min(), smear.max(), smear.size))
+    assert smear.size >= 20
+    assert smear.min() >= -88.5 and smear.max() <= -49.0
+    assert smear.min() <= -80.0 and smear.max() >= -55.0
+    # alias total power per channel starts at the predicted edge c / (d (1 + sin 26))
+    ch_alias = out[:, j0 * 256:(j0 + 1) * 256][:, south].sum(axis=(1, 2))
+    ch_main = out[:, j0 * 256 + m0].sum(axis=-1)
+    first = int(np.argmax(ch_alias > 0.25 * ch_main))
+    assert abs(F_ALL[first] - C0 / (D * (1 + v))) < 8e6
+    idx = np.array([100, 683, 700, 1023])
+    ref = oracle_mod.beamform(oracle_mod.Geometry(), F_ALL[idx], raw[:, idx])[0]
+    err = np.abs(out[idx] - ref).max(axis=(1, 2)) / ref.max(axis=(1, 2))
+    assert err.max() <= TOL[precision], err

@@ -527,3 +527,35 @@ def test_upchan128_tone_grouping(oracle_mod):
         assert want == (q + (off + 4) // 8) % 16  # -4 .. +3 keep q, +4 .. +11 go up one
         assert int(np.argmax(tot[i])) == want, (q, off, tot[i])
         assert tot[i, want] >= 0.99 * tot[i].sum(), (q, off)
+
+
+def test_frequency_summed_map_against_closed_form(oracle_mod):
+    """Sec. 3.3 / Fig. 3: the oracle's beams summed over channels (every 32nd channel of
+    the band, noiseless 4-bit frames of a source at 26 deg N-S, 0.2 deg E-W) have the
+    shape of the closed-form N-S x E-W array factors summed over the same channels:
+    peak in the source's pointing and E-W beam, alias south of zenith at the predicted
+    fraction of the main beam.  A dropped E-W weight, a mis-signed N-S phase or a wrong
+    bin would move or reshape the map."""
+    f = synth.chan_freq_hz(np.arange(8, 1024, 32))
+    s26 = math.sin(math.radians(26.0))
+    raw = synth.point_source_frames(f, s26, phi_deg=0.2)
+    out = oracle_mod.beamform(oracle_mod.Geometry(), f, raw)[0]
+    m_map = out.sum(axis=(0, 2)).reshape(4, 256)
+    sin_m = (np.arange(256) - 127.5) / 128
+    v = math.cos(math.radians(0.2)) * s26
+    kappa = 512 * f * D * v / C0
+    bins = np.mod(np.floor(512 * f[:, None] * D * sin_m[None, :] / C0 + 0.5).astype(np.int64), 512)
+    n = np.arange(256)
+    af_ns = np.abs(np.exp(2j * np.pi * (kappa[:, None, None] - bins[:, :, None]) * n / 512)
+                   .sum(axis=2)) ** 2
+    x = (np.arange(4) - 1.5) * 20.0
+    sphi = np.sin(np.deg2rad((np.arange(4) - 1.5) * 0.4))
+    u = math.sin(math.radians(0.2))
+    af_ew = np.abs(np.exp(2j * np.pi * f[:, None, None] * x[None, None, :] * (u - sphi)[None, :, None]
+                          / C0).sum(axis=2)) ** 2
+    pred = np.einsum("fj,fm->jm", af_ew, af_ns)
+    assert np.unravel_index(np.argmax(m_map), m_map.shape) == (2, 184)
+    assert np.abs(m_map / m_map.max() - pred / pred.max()).max() <= 0.005
+    south = sin_m < 0
+    r, rp = m_map[2][south].max() / m_map.max(), pred[2][south].max() / pred.max()
+    assert 0.005 < rp < 0.1 and abs(r - rp) <= 0.05 * rp
