@@ -427,8 +427,18 @@ __device__ __forceinline__ uint32_t load_word(__amdgpu_buffer_rsrc_t r, int lane
     return __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, row_off, 0);
 }
 
+// This thread's words of sample phase u = 0 of a 128-sample block (the same for
+// every bin k of the block: loaded once per block, ahead of use).
+__device__ __forceinline__ void load_phase0(__amdgpu_buffer_rsrc_t src, int blk_off, int t,
+                                            uint32_t (&w)[16])
+{
+#pragma unroll
+    for (int tau = 0; tau < 16; ++tau) w[tau] = load_word(src, 4 * t, blk_off + 8 * tau * kInputs);
+}
+
 template <int S0>
 __device__ __forceinline__ void time_dft128(__amdgpu_buffer_rsrc_t src, int blk_off,
+                                            const uint32_t (&phase0)[16],
                                             const float2* __restrict__ twk,
                                             float4* __restrict__ T, int t)
 {
@@ -437,7 +447,7 @@ __device__ __forceinline__ void time_dft128(__amdgpu_buffer_rsrc_t src, int blk_
     float2 Z[8][4];  // [u][input byte e]
     uint32_t raw[16], nxt[16];
 #pragma unroll
-    for (int tau = 0; tau < 16; ++tau) nxt[tau] = load_word(src, 4 * t, blk_off + 8 * tau * kInputs);
+    for (int tau = 0; tau < 16; ++tau) nxt[tau] = phase0[tau];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         // one phase u at a time: without the barrier the scheduler hoists every
@@ -508,13 +518,14 @@ __device__ __forceinline__ void time_dft128(__amdgpu_buffer_rsrc_t src, int blk_
 }
 
 __device__ __forceinline__ void time_dft128_bin(int k, __amdgpu_buffer_rsrc_t src, int blk_off,
-                                                const float2* twk, float4* T, int t)
+                                                const uint32_t (&phase0)[16], const float2* twk,
+                                                float4* T, int t)
 {
     switch (k & 3) {
-    case 0: time_dft128<0>(src, blk_off, twk, T, t); break;
-    case 1: time_dft128<1>(src, blk_off, twk, T, t); break;
-    case 2: time_dft128<2>(src, blk_off, twk, T, t); break;
-    default: time_dft128<3>(src, blk_off, twk, T, t); break;
+    case 0: time_dft128<0>(src, blk_off, phase0, twk, T, t); break;
+    case 1: time_dft128<1>(src, blk_off, phase0, twk, T, t); break;
+    case 2: time_dft128<2>(src, blk_off, phase0, twk, T, t); break;
+    default: time_dft128<3>(src, blk_off, phase0, twk, T, t); break;
     }
 }
 

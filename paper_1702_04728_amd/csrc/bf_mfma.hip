@@ -403,10 +403,13 @@ void bf_mfma_up128_kernel(LaunchArgs a)
             for (int i = 0; i < 4; ++i) acc[j][nu][i] = 0.f;
 
     const int n_blk128 = a.n_time / 128;
+    uint32_t phase0[16];  // the block's first sample phase, loaded a block ahead
+    load_phase0(src, 0, t, phase0);
     for (int blk = 0; blk < n_blk128; ++blk) {
         for (int i = 0; i < 8; ++i) {
             const int k = k128_of(wk.par, i);
-            time_dft128_bin(k, src, blk * 128 * kInputs, a.tw128k + k * 32, s_T, t);
+            time_dft128_bin(k, src, blk * 128 * kInputs, phase0, a.tw128k + k * 32, s_T, t);
+            if (i == 7 && blk + 1 < n_blk128) load_phase0(src, (blk + 1) * 128 * kInputs, t, phase0);
             __syncthreads();
             half8 A[4][2];
             [[maybe_unused]] half8 Alo[4][2];
