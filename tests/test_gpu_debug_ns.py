@@ -69,3 +69,35 @@ def test_detected_beams_equal_frame_output(torch_mod, bfm, precision):
         lut = bfm.compute_lut(freqs)
         # outputs gather bins through the Eq. (1) table; the beams hold them per m
         assert np.allclose(pw[:, s], ref, rtol=1e-5, atol=0), (s, lut.shape)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_ns_stage_alone_against_numpy_fft(torch_mod, bfm, precision):
+    """The N-S stage on its own (Sec. 3.1): only cylinder 0 carries signal, constant
+    over one 16-sample block, and all E-W directions are 0 (every weight exactly 1), so
+    every E-W beam is cylinder 0's line and the time DFT is 16 x the sample in bin 0 and
+    exactly 0 elsewhere.  Bin 0's beams must equal 16 x the zero-padded 512-point FFT of
+    the 256 feeds (numpy's, a library routine independent of both the oracle and the
+    kernels) at the Eq. (1) bins of every channel."""
+    rng = np.random.default_rng(55)
+    freqs = synth.chan_freq_hz([40, 512, 990])
+    n_chan = len(freqs)
+    x = rng.integers(-8, 8, (n_chan, 256, 2)) + 1j * rng.integers(-8, 8, (n_chan, 256, 2))
+    raw1 = np.full((n_chan, 16, 2048), 0x88, dtype=np.uint8)
+    code = (((x.real + 8).astype(np.uint8) << 4) | (x.imag + 8).astype(np.uint8)).reshape(n_chan, 512)
+    raw1[:, :, :512] = code[:, None, :]                     # inputs (0 * 256 + n) * 2 + p
+    print("debug_ns N-S alone: %s precision %s" % (raw1.shape, precision), flush=True)
+    with bfm.Beamformer(freqs, precision=precision, n_time=16, sin_phi_ew=np.zeros(4)) as b:
+        u = b.debug_ns(torch_mod.from_numpy(raw1).cuda()).cpu().numpy().astype(np.complex128)
+    assert u.shape == (n_chan, 1, 16, 2, 4, 256)
+    assert not np.any(u[:, :, 1:])                          # time-DFT bins s != 0: exactly 0
+    sin_m = (np.arange(256) - 127.5) / 128
+    for c, f in enumerate(freqs):
+        k = np.mod(np.floor(512 * f * 0.3048 * sin_m / 299_792_458.0 + 0.5).astype(np.int64), 512)
+        for p in range(2):
+            ref = 16 * np.fft.fft(x[c, :, p], 512)[k]
+            got = u[c, 0, 0, p]                             # [j][m]
+            for j in range(4):
+                err = np.abs(got[j] - ref).max() / np.abs(ref).max()
+                assert err <= TOL[precision], (c, p, j, err)
+            assert np.array_equal(got[0], got[3]) and np.array_equal(got[1], got[2])
