@@ -66,6 +66,23 @@ def test_uniform_bytes_parity(torch_mod, bfm, oracle_mod, n_frames, n_chan, seed
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16", "fp32_mfma"])
+@pytest.mark.parametrize("n_time", [128, 640])
+def test_other_frame_lengths(torch_mod, bfm, oracle_mod, n_time, precision):
+    """One 128-sample block per frame (the smallest the 128-point form takes) and five
+    (a frame longer than the paper's): the kernel's block loop at both ends.  As for the
+    16-point form, frames shorter than 0.983 ms integrate few terms, so the FP16 error is
+    normalised by max(P_ref, median P_ref) there (R17)."""
+    raw = synth.uniform_bytes(47 + n_time, (2, 2, n_time, 2048))
+    freqs = synth.chan_freq_hz([150, 930])
+    got = _run(torch_mod, bfm, raw, freqs, 128, precision=precision)
+    ref = oracle_mod.beamform_upchan128(oracle_mod.Geometry(n_time=n_time), freqs, raw)
+    den = ref if (precision != "fp16" or n_time >= 384) else np.maximum(ref, np.median(ref))
+    err = np.abs(got - ref) / den
+    print("upchan128 n_time %d %s max rel err %.3e" % (n_time, precision, err.max()))
+    assert err.max() <= TOLS[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp32_mfma"])
 @pytest.mark.parametrize("cyl_x", [None, (-31.0, -9.5, 10.25, 29.0)])
 def test_general_geometry_parity(torch_mod, bfm, oracle_mod, precision, cyl_x):
     """E-W directions without mirror symmetry, with the default (symmetric) cylinders
