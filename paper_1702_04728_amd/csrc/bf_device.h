@@ -200,22 +200,19 @@ __device__ __forceinline__ uint32_t add3_u32(uint32_t a, uint32_t b, uint32_t c)
 // distinct 16-byte bank groups per 16 lanes, without it the writes hit 4.
 __device__ __forceinline__ int tslot(int sigma) { return sigma ^ ((sigma >> 4) & 3); }
 
-// One 16-sample block of this thread's 8 inputs (bytes 8t .. 8t+7 of each
-// sample): time-DFT bins s = S0 + 4 s2, s2 = 0..3, by a radix-4 split of the
-// 16-point DFT:
+// Integer part of the class-S0 time DFT of this thread's 8 inputs (bytes
+// 8t .. 8t+7 of each sample row, or whichever 8 consecutive bytes raw holds):
 //   y[t1] = sum_t2 x[t1 + 4 t2] (-i)^(t2 S0)        (4-point DFT over the stride)
-//   T[s2] = sum_t1 (y[t1] w16^(t1 S0)) (-i)^(t1 s2)
-// y is formed on the raw nibbles four inputs at a time (bytewise integer
-// sums in a 32-bit word, biased so no byte borrows), converted to float once.
-// Output: T[s2 * 1024 + tslot(slot)], slot = cyl * 256 + feed, float4 = both pols.
+// formed on the raw nibbles four inputs at a time, as bytewise integer sums
+// in a 32-bit word biased so that no byte borrows: byte k of yr[t1][w]
+// (yi[t1][w]) is Re (Im) y[t1] + 32 of input 4 w + k, in every class.
 template <int S0>
-__device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restrict__ T, int t)
+__device__ __forceinline__ void time_y(const uint2 (&raw)[16], uint32_t (&yr)[4][2], uint32_t (&yi)[4][2])
 {
-    // nibble planes: re[tau][w], im[tau][w] hold the 4 offset-binary nibbles
-    // (value + 8) of inputs 8t + 4w .. 8t + 4w + 3 as bytes
+    // nibble planes: r, m hold the 4 offset-binary nibbles (value + 8) of
+    // inputs 4w .. 4w + 3 as bytes
     constexpr uint32_t kLo = 0x0f0f0f0fu;
     constexpr uint32_t kBias = 0x20202020u;  // +32 per byte keeps differences >= 0
-    uint32_t yr[4][2], yi[4][2];
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
 #pragma unroll
@@ -243,6 +240,31 @@ __device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restr
             }
         }
     }
+}
+
+__device__ __forceinline__ void time_y_class(int s0, const uint2 (&raw)[16], uint32_t (&yr)[4][2],
+                                             uint32_t (&yi)[4][2])
+{
+    switch (s0) {
+    case 0: time_y<0>(raw, yr, yi); break;
+    case 1: time_y<1>(raw, yr, yi); break;
+    case 2: time_y<2>(raw, yr, yi); break;
+    default: time_y<3>(raw, yr, yi); break;
+    }
+}
+
+// One 16-sample block of this thread's 8 inputs (bytes 8t .. 8t+7 of each
+// sample): time-DFT bins s = S0 + 4 s2, s2 = 0..3, by a radix-4 split of the
+// 16-point DFT:
+//   y[t1] = sum_t2 x[t1 + 4 t2] (-i)^(t2 S0)        (time_y)
+//   T[s2] = sum_t1 (y[t1] w16^(t1 S0)) (-i)^(t1 s2)
+// y is converted to float once.
+// Output: T[s2 * 1024 + tslot(slot)], slot = cyl * 256 + feed, float4 = both pols.
+template <int S0>
+__device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restrict__ T, int t)
+{
+    uint32_t yr[4][2], yi[4][2];
+    time_y<S0>(raw, yr, yi);
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
         float2 o[2][4];
@@ -295,6 +317,13 @@ __device__ __forceinline__ void load_block(const uint8_t* __restrict__ blk, uint
 #pragma unroll
     for (int tau = 0; tau < 16; ++tau)
         raw[tau] = *reinterpret_cast<const uint2*>(blk + tau * stride + 8 * t);
+}
+// The same with an arbitrary 8-byte-aligned offset into each sample row.
+__device__ __forceinline__ void load_block_at(const uint8_t* __restrict__ blk, uint2 (&raw)[16], int off)
+{
+#pragma unroll
+    for (int tau = 0; tau < 16; ++tau)
+        raw[tau] = *reinterpret_cast<const uint2*>(blk + tau * kInputs + off);
 }
 
 // Samples of 16-sample block `it`.

@@ -261,38 +261,136 @@ __device__ __forceinline__ void ns_stage2(const half8& Bh, const half8& Bl, cons
     }
 }
 
+// cos and sin of 2 pi k / 16.
+__constant__ float kCos16[16] = {1.f, kC16_1, kR2, kS16_1, 0.f, -kS16_1, -kR2, -kC16_1,
+                                 -1.f, -kC16_1, -kR2, -kS16_1, 0.f, kS16_1, kR2, kC16_1};
+__constant__ float kSin16[16] = {0.f, kS16_1, kR2, kC16_1, 1.f, kC16_1, kR2, kS16_1,
+                                 0.f, -kS16_1, -kR2, -kC16_1, -1.f, -kC16_1, -kR2, -kS16_1};
+
+// The last step of the class-s0 time DFT and E-W phasing together are one
+// complex 16 x 16 matrix per (channel, class), applied to each (feed, pol):
+//   b[s2][j] = sum_c W[j][c] sum_t1 w16^(t1 (s0 + 4 s2)) y_c[t1]
+// (y_c[t1] the stride-4 sums of cylinder c, time_y; s0 + 4 s2 the
+// sub-channel, j the E-W beam).  As a real 32 x 32 block on the matrix cores:
+// K = (cylinder c, t1, re/im) with lane (c, .) holding cylinder c's 8 values,
+// columns (s2, j) = 4 s2 + j, N-tile 0 giving the real and N-tile 1 the
+// imaginary part of b.  The y values are small integers, exact in FP16; the
+// matrix is carried as hi + lo (two MFMAs per tile), so the E-W output keeps
+// ~22 significant bits before the N-S transform.  Entries formed in FP32
+// from the weight row W[j][c] (ew_row, [4][4]) at the start of the frame,
+// each rounded to FP32 once and then split: left to itself the compiler
+// folds some of the hi conversions into the products' fused multiply-adds
+// (one rounding from the exact value) and not the lo subtractions, and where
+// the FP32 value is an FP16 rounding tie the two hi values then differ by one
+// FP16 ulp, which hi + lo keeps.
+__device__ __forceinline__ void load_ew_mats(const float2* __restrict__ ew_row, int s0, int lane,
+                                             half8 (&Gh)[2], half8 (&Gl)[2])
+{
+    const int c = lane >> 4, col = lane & 15;
+    const int j = col & 3, s = s0 + 4 * (col >> 2);
+    const float2 wjc = ew_row[j * kCyl + c];
+#pragma unroll
+    for (int t1 = 0; t1 < 4; ++t1) {
+        const int k = (t1 * s) & 15;
+        const float2 m = cmul(wjc, make_float2(kCos16[k], -kSin16[k]));  // W[j][c] w16^(t1 s)
+        // real output: Re y m.x - Im y m.y; imaginary output: Re y m.y + Im y m.x
+        const float v[2][2] = {{m.x, -m.y}, {m.y, m.x}};
+#pragma unroll
+        for (int nu = 0; nu < 2; ++nu)
+#pragma unroll
+            for (int ri = 0; ri < 2; ++ri) {
+                float x = v[nu][ri];
+                asm volatile("" : "+v"(x));
+                const _Float16 hi = (_Float16)x;
+                Gh[nu][2 * t1 + ri] = hi;
+                Gl[nu][2 * t1 + ri] = (_Float16)(x - (float)hi);
+            }
+    }
+}
+
+// A fragment of input 4 wd + m of this lane (K = (t1, re/im) of its
+// cylinder): y[t1] exactly, from the biased bytes of time_y.  One byte
+// permute places Re and Im of one t1 into the low bytes of two halves, the
+// exponent bits of 1024 make each half 1024 + byte, and one packed FP16
+// subtraction of 1024 + 32 leaves y.
+__device__ __forceinline__ half8 y_fragment(const uint32_t (&yr)[4][2], const uint32_t (&yi)[4][2], int wd,
+                                            int m)
+{
+    const uint32_t sel = 0x0c000c00u | ((4u + m) << 16) | (uint32_t)m;  // (yr byte m, 0, yi byte m, 0)
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 d;
+#pragma unroll
+    for (int t1 = 0; t1 < 4; ++t1) d[t1] = __builtin_amdgcn_perm(yi[t1][wd], yr[t1][wd], sel) | 0x64006400u;
+    const half8 bias = {1056.f16, 1056.f16, 1056.f16, 1056.f16, 1056.f16, 1056.f16, 1056.f16, 1056.f16};
+    return __builtin_bit_cast(half8, d) - bias;
+}
+
+// hi = fp16 pair (x, y), lo = fp16 pair (x - hi.x, y - hi.y) (see split_half8),
+// for x, y straight from matrix-core accumulators.  The hi conversion reads
+// them in code the compiler sees, so it waits for the matrix instruction's
+// result there (no opaque copy first, unlike split_half8: an MFMA result
+// cannot be folded into a conversion anyway); the lo asm comes after it.
+__device__ __forceinline__ void split_pair(float x, float y, uint32_t& hi, uint32_t& lo)
+{
+    half2v hp;
+    hp[0] = (_Float16)x;
+    hp[1] = (_Float16)y;
+    hi = __builtin_bit_cast(uint32_t, hp);
+    asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixhi_f16 %0, %1, -1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+        : "=&v"(lo)
+        : "v"(hi), "v"(x), "v"(y));
+}
+
+// E-W output in LDS, one line (E-W beam j, pol p, sub-channel s0 + 4 s2) per
+// kLineStride dwords, line 16 p + 4 s2 + j; each dword one complex FP16
+// value (re low); feed 16 a + b at dword 16 b + 4 ((a >> 2) ^ ((b >> 2) & 3))
+// + (a & 3), so the stage-1 reads (four consecutive a per lane, 16 b per
+// quarter-wave) and the E-W writes (4 a x 16 lines per instruction) each
+// spread over all banks.
+constexpr int kLineStride = 260;
+constexpr int kELines = 32;
+
 // kSplitV: also carry the E-W output as hi + lo (stage 1 sums hi*hi + lo*hi +
 // hi*lo): every operand then holds ~22 significant bits and the result is
 // FP32-class (max relative power error ~1e-6 against FP64).
 // kFine: the pre-detection beams (each line's kept beams written out instead
 // of its power summed).
-template <int kEw, bool kSplitV, bool kFine>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+//
+// Per 16-sample block: each wave takes the 128 (feed, pol) pairs 128 w ..
+// 128 w + 127 of all four cylinders (lane (c, r) reads cylinder c's bytes
+// 128 w + 8 r .. + 7 of every sample row), forms their stride-4 sums (time_y)
+// and, per input e of the lane, one matrix-core tile of 16 (feed, pol) rows x
+// (all 4 sub-channels x 4 E-W beams) into LDS; then wave w takes sub-channel
+// s0 + 4 w's 8 lines through the four-step N-S transform and |.|^2.
+// (The FP32-class debug form needs more than half the LDS of a CU, so it runs
+// one workgroup per CU.)
+template <bool kSplitV, bool kFine>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kSplitV && kFine ? 1 : 2, 2)))
 void bf_mfma_kernel(LaunchArgs a)
 {
-    __shared__ __align__(16) float4 s_T[4 * 1024];  // time-DFT output, then per-bin powers
+    __shared__ __align__(16) uint32_t s_E[(kSplitV ? 2 : 1) * kELines * kLineStride];
     __shared__ __align__(16) float2 s_bins[kFine ? 4 * 512 : 1];  // per wave: one line's bins
+    static_assert(sizeof(s_E) >= 4 * 4 * 512 * sizeof(float), "E-W area must hold the per-bin powers");
 
     const Work wk = work_of_block();
     UnitIO io;
     if (!resolve_unit(a, wk, io)) return;
     const int t = threadIdx.x;
-    const int lane = t & 63, s2 = t >> 6, q = lane >> 4, n = lane & 15;
+    const int lane = t & 63, w = t >> 6, q = lane >> 4, n = lane & 15;
 
     NsTables mt;
     load_ns_tables(a.mf, mt, lane);
-    float2 W[4][4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) W[j][c] = a.ew[((size_t)io.ew_row * kBeamEW + j) * kCyl + c];
+    half8 Gh[2], Gl[2];
+    load_ew_mats(a.ew + (size_t)io.ew_row * kBeamEW * kCyl, wk.s0, lane, Gh, Gl);
 
     int32_t lv[kFine ? 4 : 1] = {};  // bin-table entries of the beams this lane writes
     if constexpr (kFine) load_lut_lane<4>(a.lut + (size_t)io.row * kBeamNS, lv, lane);
 
     const uint8_t* src = io.in;
+    const int in_off = 512 * q + 128 * w + 8 * n;  // cylinder q, (feed, pol) 128 w + 8 n + e
     uint2 raw[16];
-    load_block(block_base(src, 0), raw, t);
+    load_block_at(block_base(src, 0), raw, in_off);
 
     float acc[4][2][4];  // [E-W beam j][c = n + 16 nu][d = 4 q + i]
     constexpr int kAcc = sizeof(acc) / sizeof(float);
@@ -307,14 +405,57 @@ void bf_mfma_kernel(LaunchArgs a)
         load_partial<kAcc>(&acc[0][0][0], io.partial, t);
     }
 
+    uint32_t* const E = s_E;
+    [[maybe_unused]] uint32_t* const Elo = s_E + kELines * kLineStride;
     for (int blk = 0; blk < a.n_blk; ++blk) {
-        time_dft_class(wk.s0, raw, s_T, t);
-        __syncthreads();
-        if (blk + 1 < a.n_blk) load_block(block_base(src, blk + 1), raw, t);
+        uint32_t yr[4][2], yi[4][2];
+        time_y_class(wk.s0, raw, yr, yi);
+        if (blk + 1 < a.n_blk) load_block_at(block_base(src, blk + 1), raw, in_off);
 
+        // time-DFT tail + E-W phasing: tile e = input e of each lane; output
+        // row 4 q + i is feed 16 (4 w + q) + 4 i + (e >> 1), pol e & 1, of
+        // column n = (s2, j)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const half8 Ay = y_fragment(yr, yi, e >> 2, e & 3);
+            const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+            floatx4 Xr = mfma16(Ay, Gh[0], zero);
+            Xr = mfma16(Ay, Gl[0], Xr);
+            floatx4 Xi = mfma16(Ay, Gh[1], zero);
+            Xi = mfma16(Ay, Gl[1], Xi);
+            const int line = (16 * (e & 1) + n) * kLineStride;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int pos = line + 16 * (4 * i + (e >> 1)) + 4 * (w ^ i) + q;
+                if constexpr (kSplitV) {
+                    uint32_t hi, lo;
+                    split_pair(Xr[i], Xi[i], hi, lo);
+                    E[pos] = hi;
+                    Elo[pos] = lo;
+                } else {
+                    half2v hp;
+                    hp[0] = (_Float16)Xr[i];
+                    hp[1] = (_Float16)Xi[i];
+                    E[pos] = __builtin_bit_cast(uint32_t, hp);
+                }
+            }
+        }
+        __syncthreads();
+
+        // stage-1 A fragments of this wave's 8 lines: lane (q, n) holds feeds
+        // 16 a + n, a = 4 q .. 4 q + 3
         half8 A[4][2];
         [[maybe_unused]] half8 Alo[4][2];
-        ew_fragments<kEw, kSplitV>(s_T + s2 * 1024, W, A, Alo, q, n);
+        const int rd = 16 * n + 4 * (q ^ (n >> 2));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int pos = (16 * p + 4 * w + j) * kLineStride + rd;
+                A[j][p] = __builtin_bit_cast(half8, *reinterpret_cast<const uint4*>(E + pos));
+                if constexpr (kSplitV)
+                    Alo[j][p] = __builtin_bit_cast(half8, *reinterpret_cast<const uint4*>(Elo + pos));
+            }
         __syncthreads();
 
 #pragma unroll
@@ -328,7 +469,7 @@ void bf_mfma_kernel(LaunchArgs a)
                     floatx4 X[2];
                     ns_stage2(Bh[nu], Bl[nu], mt, X);
                     if constexpr (kFine) {  // bin n + 16 nu + 32 (4 q + i): (re, im) = (X[0], X[1])
-                        float2* bins = s_bins + s2 * 512;
+                        float2* bins = s_bins + w * 512;
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
                             bins[n + 16 * nu + 32 * (4 * q + i)] = make_float2(X[0][i], X[1][i]);
@@ -340,8 +481,8 @@ void bf_mfma_kernel(LaunchArgs a)
                 }
                 if constexpr (kFine) {
                     wave_lds_sync();
-                    write_fine_line<4>(s_bins + s2 * 512, lv,
-                                       fine_line_ptr(a, wk.unit, blk, wk.s0 + 4 * s2, p * 4 + j), lane);
+                    write_fine_line<4>(s_bins + w * 512, lv,
+                                       fine_line_ptr(a, wk.unit, blk, wk.s0 + 4 * w, p * 4 + j), lane);
                     wave_lds_sync();
                 }
             }
@@ -353,14 +494,14 @@ void bf_mfma_kernel(LaunchArgs a)
         return;
     }
     // per-bin powers -> LDS (bin k = c + 32 d), then gather into out[beam][q]
-    float* P = reinterpret_cast<float*>(s_T);
+    float* P = reinterpret_cast<float*>(s_E);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int nu = 0; nu < 2; ++nu)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                P[(s2 * 4 + j) * 512 + n + 16 * nu + 32 * (4 * q + i)] = acc[j][nu][i];
+                P[(w * 4 + j) * 512 + n + 16 * nu + 32 * (4 * q + i)] = acc[j][nu][i];
     __syncthreads();
     write_output(P, a, io, wk.s0, t);
 }
@@ -471,22 +612,13 @@ hipError_t launch_mfma(const LaunchArgs& a, hipStream_t stream)
     if (a.n_units <= 0) return hipSuccess;
     LaunchArgs args = a;
     void* params[] = {&args};
-    // [E-W form][split][fine]
-    static const void* const kKernels[3][2][2] = {
-        {{reinterpret_cast<const void*>(&bf_mfma_kernel<kEwGeneral, false, false>),
-          reinterpret_cast<const void*>(&bf_mfma_kernel<kEwGeneral, false, true>)},
-         {reinterpret_cast<const void*>(&bf_mfma_kernel<kEwGeneral, true, false>),
-          reinterpret_cast<const void*>(&bf_mfma_kernel<kEwGeneral, true, true>)}},
-        {{reinterpret_cast<const void*>(&bf_mfma_kernel<kEwCyl, false, false>),
-          reinterpret_cast<const void*>(&bf_mfma_kernel<kEwCyl, false, true>)},
-         {reinterpret_cast<const void*>(&bf_mfma_kernel<kEwCyl, true, false>),
-          reinterpret_cast<const void*>(&bf_mfma_kernel<kEwCyl, true, true>)}},
-        {{reinterpret_cast<const void*>(&bf_mfma_kernel<kEwMirror, false, false>),
-          reinterpret_cast<const void*>(&bf_mfma_kernel<kEwMirror, false, true>)},
-         {reinterpret_cast<const void*>(&bf_mfma_kernel<kEwMirror, true, false>),
-          reinterpret_cast<const void*>(&bf_mfma_kernel<kEwMirror, true, true>)}}};
-    const int ew = a.sym_ew ? kEwMirror : a.cyl_sym ? kEwCyl : kEwGeneral;
-    const void* k = kKernels[ew][a.split_v ? 1 : 0][a.fine ? 1 : 0];
+    // [split][fine]; every E-W geometry takes the same matrix-core form
+    static const void* const kKernels[2][2] = {
+        {reinterpret_cast<const void*>(&bf_mfma_kernel<false, false>),
+         reinterpret_cast<const void*>(&bf_mfma_kernel<false, true>)},
+        {reinterpret_cast<const void*>(&bf_mfma_kernel<true, false>),
+         reinterpret_cast<const void*>(&bf_mfma_kernel<true, true>)}};
+    const void* k = kKernels[a.split_v ? 1 : 0][a.fine ? 1 : 0];
     return hipLaunchKernel(k, dev::grid_for(a.n_units), dim3(dev::kThreads), params, 0, stream);
 }
 

@@ -101,3 +101,37 @@ def test_ns_stage_alone_against_numpy_fft(torch_mod, bfm, precision):
                 err = np.abs(got[j] - ref).max() / np.abs(ref).max()
                 assert err <= TOL[precision], (c, p, j, err)
             assert np.array_equal(got[0], got[3]) and np.array_equal(got[1], got[2])
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("directions", ["default", "tracking_tie"])
+def test_impulse_beams_equal_weight_times_phase(torch_mod, bfm, oracle_mod, precision, directions):
+    """Time DFT and E-W phasing together (Sec. 3, Sec. 3.1), closed form: block k holds a
+    single sample of value 7 at sample t1 = k mod 4 of cylinder c = k div 4, feed 0, pol 0,
+    so every kept beam of sub-channel s and E-W beam j must be 7 W[j][c] w16^(s t1) (feed 0
+    has N-S phase 1 in every bin), pol 1 and the empty blocks exactly 0.  The tracking
+    directions are the bench's last frame, whose weights at 650 MHz put an entry of
+    W[3][c] w16^(s t1) on an FP16 rounding tie (0.46838...): the matrix-core paths carry
+    those products as FP16 hi + lo pairs, which must come from one FP32 value."""
+    freqs = np.array([450e6, 550e6, 650e6, 750e6])
+    if directions == "default":
+        sin_phi = None
+        geom = oracle_mod.Geometry()
+    else:
+        phi = 0.3 + (15.0 / 3600.0) * 384 * 2.56e-6 * 127
+        sin_phi = synth.tracking_pointings([phi])[0]
+        geom = oracle_mod.Geometry(sin_phi_ew=sin_phi)
+    raw1 = np.full((4, 384, 2048), 0x88, dtype=np.uint8)
+    for k in range(16):
+        raw1[:, 16 * k + (k & 3), (k >> 2) * 512] = 0xF8       # value 7 + 0i
+    print("debug_ns impulses: %s directions, precision %s" % (directions, precision), flush=True)
+    with bfm.Beamformer(freqs, precision=precision, sin_phi_ew=sin_phi) as b:
+        u = b.debug_ns(torch_mod.from_numpy(raw1).cuda()).cpu().numpy().astype(np.complex128)
+    assert not np.any(u[:, 16:]) and not np.any(u[:, :, :, 1])
+    s = np.arange(16)
+    for ch, f in enumerate(freqs):
+        W = oracle_mod.ew_weights(geom, f)                       # [j][c]
+        for k in range(16):
+            ref = 7 * W[None, :, k >> 2] * np.exp(-2j * np.pi * s * (k & 3) / 16)[:, None]
+            err = np.abs(u[ch, k, :, 0] - ref[:, :, None]).max() / 7
+            assert err <= TOL[precision], (ch, k, err)
