@@ -19,16 +19,17 @@
 // Decomposition: one workgroup (256 threads) per (channel-frame, s0), where
 // s0 in [0, 4) selects the sub-channels s = s0 + 4*s2 (s2 in [0, 4)).  Per
 // 16-sample block:
-//   A  each thread reads 16 samples of 8 consecutive inputs, forms its four
-//      time-DFT outputs via a radix-4 split (a DFT-4 over the sample stride,
-//      a twiddle, a DFT-4 over the sample phase), writes them to LDS;
-//   B1 each 16-lane group (s2, jp, p) forms the E-W beams j = jp and 3 - jp
-//      of polarisation p while reading its lines (lane b holds feeds 16a + b).
-//      With the mirror-symmetric default geometry the pair shares its sums:
-//      S_c = y_c + y_(3-c), D_c = y_c - y_(3-c), beam jp = P + iQ and beam
-//      3 - jp = P - iQ with P = sum_c Re W[jp][c] S_c, Q = sum_c Im W[jp][c] D_c
-//      (c = 0, 1), 20 instead of 32 operations per feed and pair; any other
-//      geometry (kSym false) forms both beams from the full four-cylinder sums;
+//   A  wave w takes (feed, pol) pairs 128 w .. 128 w + 127 of all four
+//      cylinders: each lane reads 16 samples of 8 consecutive inputs of one
+//      cylinder and forms their stride-4 sums (a DFT-4 over the sample stride,
+//      exact integers); the rest of the time DFT (a twiddle and a DFT-4 over
+//      the sample phase) and E-W phasing are then one fixed complex 16 x 16
+//      matrix per (channel, class) per (feed, pol), applied on the matrix cores
+//      (FP16 hi + lo matrix, exact integer operands, FP32 results: ~22
+//      significant bits), and the E-W beams of all four sub-channels go to LDS
+//      as FP32;
+//   B1 each 16-lane group (s2, jp, p) reads the lines of E-W beams jp and
+//      3 - jp of polarisation p (lane b holds feeds 16a + b);
 //   B2 each group transforms its two lines: 512 = 32 x 16 with the upper half
 //      of the input zero, so step 1 is a pruned 32-point DFT per lane (two
 //      16-point FFTs), then twiddles w512^(b c), a 16-lane transpose through LDS
@@ -245,12 +246,23 @@ __device__ __forceinline__ void ew_group(const float2* __restrict__ Tp, const fl
     }
 }
 
-template <bool kSym, bool kFine>
+// E-W output of the matrix-core step in LDS (float2 units): line (E-W beam j,
+// pol p, sub-channel s0 + 4 s2) 16 p + 4 s2 + j at kEwLine apart; feed 16 a + b
+// at 16 b + 2 ((a >> 1) ^ ((b >> 1) & 7)) + (a & 1), so that each group's
+// 16-byte reads of consecutive a (one b per lane) spread over all banks.
+constexpr int kEwLine = 258;
+static_assert(kUnionF2 >= 32 * kEwLine, "union region must hold the E-W output");
+__device__ __forceinline__ int ew_pos(int b, int a) { return 16 * b + 2 * ((a >> 1) ^ ((b >> 1) & 7)) + (a & 1); }
+
+template <bool kFine>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bf_fp32_kernel(LaunchArgs a)
 {
     __shared__ __align__(16) float2 s_union[kUnionF2];
     __shared__ __align__(16) float4 s_tw[16 * 16];  // [c'][b]: w512^(b 2c'), w512^(b (2c'+1))
+    // the (channel, class) matrix in fragment order [hi0, hi1, lo0, lo1][lane],
+    // read back every block (in registers it would push the kernel past 256 VGPRs)
+    __shared__ __align__(16) half8 s_G[4][64];
 
     const Work wk = work_of_block();
     UnitIO io;
@@ -260,21 +272,25 @@ void bf_fp32_kernel(LaunchArgs a)
     const int b = t & 15;
     const int s2 = g >> 2, jp = (g >> 1) & 1, pol = g & 1;
     const int jl[2] = {jp, 3 - jp};  // the group's two E-W beams
+    const int lane = t & 63, w = t >> 6, q = lane >> 4, n = lane & 15;
 
     {
         const int c2 = t >> 4, bb = t & 15;
         const float2 w0 = a.tw[(2 * c2) * 16 + bb], w1 = a.tw[(2 * c2 + 1) * 16 + bb];
         s_tw[t] = make_float4(w0.x, w0.y, w1.x, w1.y);
     }
-    float2 W[2][4];
-#pragma unroll
-    for (int l = 0; l < 2; ++l)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) W[l][c] = a.ew[((size_t)io.ew_row * kBeamEW + jl[l]) * kCyl + c];
+    if (t < 64) {
+        half8 Gh[2], Gl[2];
+        load_ew_mats(a.ew + (size_t)io.ew_row * kBeamEW * kCyl, wk.s0, lane, Gh, Gl);
+        s_G[0][lane] = Gh[0];
+        s_G[1][lane] = Gh[1];
+        s_G[2][lane] = Gl[0];
+        s_G[3][lane] = Gl[1];
+    }
+    __syncthreads();
 
     const uint8_t* src = io.in;
-    float4* T = reinterpret_cast<float4*>(s_union);
-    const float2* Tp = reinterpret_cast<const float2*>(s_union) + pol;  // this pol of T
+    const int in_off = 512 * q + 128 * w + 8 * n;  // cylinder q, (feed, pol) 128 w + 8 n + e
     float2* bufE = s_union + g * kGroupF2;
     float2* bufO = bufE + kXpBuf;
 
@@ -282,7 +298,7 @@ void bf_fp32_kernel(LaunchArgs a)
     if constexpr (kFine) load_lut_lane<16>(a.lut + (size_t)io.row * kBeamNS, lv, b);
 
     uint2 raw[16];
-    load_block(block_base(src, 0), raw, t);
+    load_block_at(block_base(src, 0), raw, in_off);
 
     float acc[2][2][16];  // [line l: beam jl[l]][E/O][d]
     constexpr int kAcc = sizeof(acc) / sizeof(float);
@@ -296,22 +312,49 @@ void bf_fp32_kernel(LaunchArgs a)
     }
 
     for (int blk = 0; blk < a.n_blk; ++blk) {
-        // A: time DFT of this thread's 8 inputs
-        time_dft_class(wk.s0, raw, T, t);
+        // A: stride-4 sums of this lane's 8 inputs, then the time-DFT tail and
+        // E-W phasing on the matrix cores; tile e = input e of each lane, output
+        // row 4 q + i = feed 16 (4 w + q) + 4 i + (e >> 1), pol e & 1, column
+        // n = (s2, j)
+        {
+            uint32_t yr[4][2], yi[4][2];
+            time_y_class(wk.s0, raw, yr, yi);
+            const half8 Gh[2] = {s_G[0][lane], s_G[1][lane]}, Gl[2] = {s_G[2][lane], s_G[3][lane]};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                floatx4 Xr, Xi;
+                ew_tile(yr, yi, e, Gh, Gl, Xr, Xi);
+                float2* line = s_union + (16 * (e & 1) + n) * kEwLine;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) line[ew_pos(4 * i + (e >> 1), 4 * w + q)] = make_float2(Xr[i], Xi[i]);
+            }
+        }
         __syncthreads();
-        // B1: E-W phasing while loading this group's feeds 16 a + b of pol p
+        // B1: this group's two lines, feeds 16 a + b
         float2 v0[16], v1[16];
-        ew_group<kSym>(Tp + 2 * s2 * 1024, W, v0, v1, b);
+        {
+            const float2* L0 = s_union + (16 * pol + 4 * s2 + jl[0]) * kEwLine;
+            const float2* L1 = s_union + (16 * pol + 4 * s2 + jl[1]) * kEwLine;
+#pragma unroll
+            for (int aa = 0; aa < 16; aa += 2) {
+                const float4 x0 = *reinterpret_cast<const float4*>(L0 + ew_pos(b, aa));
+                const float4 x1 = *reinterpret_cast<const float4*>(L1 + ew_pos(b, aa));
+                v0[aa] = make_float2(x0.x, x0.y);
+                v0[aa + 1] = make_float2(x0.z, x0.w);
+                v1[aa] = make_float2(x1.x, x1.y);
+                v1[aa + 1] = make_float2(x1.z, x1.w);
+            }
+        }
         __syncthreads();
         // B2: N-S transform of both lines, power into per-bin accumulators; the
         // next block's samples are fetched during the second line (issued
-        // there, the 32 registers they take are free for E-W phasing and the
-        // first line).  The last block fetches itself again rather than
-        // branch: one basic block schedules with fewer live registers.
+        // there, the 32 registers they take are free for the first line).  The
+        // last block fetches itself again rather than branch: one basic block
+        // schedules with fewer live registers.
         const int k = wk.s0 + 4 * s2;
         ns_line_power<kFine>(v0, acc[0], bufE, bufO, s_tw, b, lv,
                              kFine ? fine_line_ptr(a, wk.unit, blk, k, pol * 4 + jl[0]) : nullptr);
-        load_block(block_base(src, min(blk + 1, a.n_blk - 1)), raw, t);
+        load_block_at(block_base(src, min(blk + 1, a.n_blk - 1)), raw, in_off);
         ns_line_power<kFine>(v1, acc[1], bufE, bufO, s_tw, b, lv,
                              kFine ? fine_line_ptr(a, wk.unit, blk, k, pol * 4 + jl[1]) : nullptr);
         __syncthreads();
@@ -460,13 +503,9 @@ hipError_t launch_fp32(const LaunchArgs& a, hipStream_t stream)
     if (a.n_units <= 0) return hipSuccess;
     LaunchArgs args = a;
     void* params[] = {&args};
-    const void* k;
-    if (a.fine)
-        k = a.sym_ew ? reinterpret_cast<const void*>(&bf_fp32_kernel<true, true>)
-                     : reinterpret_cast<const void*>(&bf_fp32_kernel<false, true>);
-    else
-        k = a.sym_ew ? reinterpret_cast<const void*>(&bf_fp32_kernel<true, false>)
-                     : reinterpret_cast<const void*>(&bf_fp32_kernel<false, false>);
+    // every E-W geometry takes the same matrix-core form
+    const void* k = a.fine ? reinterpret_cast<const void*>(&bf_fp32_kernel<true>)
+                           : reinterpret_cast<const void*>(&bf_fp32_kernel<false>);
     return hipLaunchKernel(k, dev::grid_for(a.n_units), dim3(dev::kThreads), params, 0, stream);
 }
 

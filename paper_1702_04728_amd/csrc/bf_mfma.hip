@@ -38,14 +38,6 @@ namespace {
 
 using namespace dev;
 
-typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ floatx4 mfma16(half8 a, half8 b, floatx4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-}
-
 // Four complex values -> A/B fragment (re, im interleaved), round to nearest.
 __device__ __forceinline__ half8 pack_half8(const float2 (&v)[4])
 {
@@ -57,8 +49,6 @@ __device__ __forceinline__ half8 pack_half8(const float2 (&v)[4])
     }
     return h;
 }
-
-typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 
 // hi = fp16(v), lo = fp16(v - hi): together they carry ~22 significant bits.
 // hi is the compiler's own packed round-to-nearest conversion.  The empty asm
@@ -261,70 +251,6 @@ __device__ __forceinline__ void ns_stage2(const half8& Bh, const half8& Bl, cons
     }
 }
 
-// cos and sin of 2 pi k / 16.
-__constant__ float kCos16[16] = {1.f, kC16_1, kR2, kS16_1, 0.f, -kS16_1, -kR2, -kC16_1,
-                                 -1.f, -kC16_1, -kR2, -kS16_1, 0.f, kS16_1, kR2, kC16_1};
-__constant__ float kSin16[16] = {0.f, kS16_1, kR2, kC16_1, 1.f, kC16_1, kR2, kS16_1,
-                                 0.f, -kS16_1, -kR2, -kC16_1, -1.f, -kC16_1, -kR2, -kS16_1};
-
-// The last step of the class-s0 time DFT and E-W phasing together are one
-// complex 16 x 16 matrix per (channel, class), applied to each (feed, pol):
-//   b[s2][j] = sum_c W[j][c] sum_t1 w16^(t1 (s0 + 4 s2)) y_c[t1]
-// (y_c[t1] the stride-4 sums of cylinder c, time_y; s0 + 4 s2 the
-// sub-channel, j the E-W beam).  As a real 32 x 32 block on the matrix cores:
-// K = (cylinder c, t1, re/im) with lane (c, .) holding cylinder c's 8 values,
-// columns (s2, j) = 4 s2 + j, N-tile 0 giving the real and N-tile 1 the
-// imaginary part of b.  The y values are small integers, exact in FP16; the
-// matrix is carried as hi + lo (two MFMAs per tile), so the E-W output keeps
-// ~22 significant bits before the N-S transform.  Entries formed in FP32
-// from the weight row W[j][c] (ew_row, [4][4]) at the start of the frame,
-// each rounded to FP32 once and then split: left to itself the compiler
-// folds some of the hi conversions into the products' fused multiply-adds
-// (one rounding from the exact value) and not the lo subtractions, and where
-// the FP32 value is an FP16 rounding tie the two hi values then differ by one
-// FP16 ulp, which hi + lo keeps.
-__device__ __forceinline__ void load_ew_mats(const float2* __restrict__ ew_row, int s0, int lane,
-                                             half8 (&Gh)[2], half8 (&Gl)[2])
-{
-    const int c = lane >> 4, col = lane & 15;
-    const int j = col & 3, s = s0 + 4 * (col >> 2);
-    const float2 wjc = ew_row[j * kCyl + c];
-#pragma unroll
-    for (int t1 = 0; t1 < 4; ++t1) {
-        const int k = (t1 * s) & 15;
-        const float2 m = cmul(wjc, make_float2(kCos16[k], -kSin16[k]));  // W[j][c] w16^(t1 s)
-        // real output: Re y m.x - Im y m.y; imaginary output: Re y m.y + Im y m.x
-        const float v[2][2] = {{m.x, -m.y}, {m.y, m.x}};
-#pragma unroll
-        for (int nu = 0; nu < 2; ++nu)
-#pragma unroll
-            for (int ri = 0; ri < 2; ++ri) {
-                float x = v[nu][ri];
-                asm volatile("" : "+v"(x));
-                const _Float16 hi = (_Float16)x;
-                Gh[nu][2 * t1 + ri] = hi;
-                Gl[nu][2 * t1 + ri] = (_Float16)(x - (float)hi);
-            }
-    }
-}
-
-// A fragment of input 4 wd + m of this lane (K = (t1, re/im) of its
-// cylinder): y[t1] exactly, from the biased bytes of time_y.  One byte
-// permute places Re and Im of one t1 into the low bytes of two halves, the
-// exponent bits of 1024 make each half 1024 + byte, and one packed FP16
-// subtraction of 1024 + 32 leaves y.
-__device__ __forceinline__ half8 y_fragment(const uint32_t (&yr)[4][2], const uint32_t (&yi)[4][2], int wd,
-                                            int m)
-{
-    const uint32_t sel = 0x0c000c00u | ((4u + m) << 16) | (uint32_t)m;  // (yr byte m, 0, yi byte m, 0)
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    u32x4 d;
-#pragma unroll
-    for (int t1 = 0; t1 < 4; ++t1) d[t1] = __builtin_amdgcn_perm(yi[t1][wd], yr[t1][wd], sel) | 0x64006400u;
-    const half8 bias = {1056.f16, 1056.f16, 1056.f16, 1056.f16, 1056.f16, 1056.f16, 1056.f16, 1056.f16};
-    return __builtin_bit_cast(half8, d) - bias;
-}
-
 // hi = fp16 pair (x, y), lo = fp16 pair (x - hi.x, y - hi.y) (see split_half8),
 // for x, y straight from matrix-core accumulators.  The hi conversion reads
 // them in code the compiler sees, so it waits for the matrix instruction's
@@ -417,12 +343,8 @@ void bf_mfma_kernel(LaunchArgs a)
         // column n = (s2, j)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const half8 Ay = y_fragment(yr, yi, e >> 2, e & 3);
-            const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
-            floatx4 Xr = mfma16(Ay, Gh[0], zero);
-            Xr = mfma16(Ay, Gl[0], Xr);
-            floatx4 Xi = mfma16(Ay, Gh[1], zero);
-            Xi = mfma16(Ay, Gl[1], Xi);
+            floatx4 Xr, Xi;
+            ew_tile(yr, yi, e, Gh, Gl, Xr, Xi);
             const int line = (16 * (e & 1) + n) * kLineStride;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {

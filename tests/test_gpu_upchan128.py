@@ -133,12 +133,17 @@ def test_batch_split_matches_one_call(torch_mod, bfm, oracle_mod):
 def test_closed_form_relations_to_16_point(torch_mod, bfm):
     """Channel-centre tone (exact integer samples): sub-channel 8 only, 8 times the
     16-point power (3 x 128^2 against 24 x 16^2); uniform bytes: total power 8 times
-    the 16-point total (Parseval)."""
+    the 16-point total (Parseval).  The tone's beams span 100 dB (2e-10 of the peak
+    power at the weakest), and the two forms round differently before the N-S
+    transform (FP32 E-W sums against matrix-core products), so beyond the relative
+    bound the relation holds to FP32 rounding of the peak: 1e-6 of the peak power."""
     tone = np.empty((1, 1, 384, 2048), np.uint8)
     synth.channel_frames(None, 600e6, 1, [synth.Source(0.3, 0.2, 3.0)], tone[:, 0], sigma=0.0)
     a16 = _run(torch_mod, bfm, tone, [600e6], 16)[0, 0]
     a128 = _run(torch_mod, bfm, tone, [600e6], 128)[0, 0]
-    assert np.allclose(a128[:, 8], 8 * a16[:, 8], rtol=TOL, atol=0)
+    assert np.allclose(a128[:, 8], 8 * a16[:, 8], rtol=TOL, atol=1e-6 * a128[:, 8].max())
+    strong = a128[:, 8] >= 1e-3 * a128[:, 8].max()
+    assert np.allclose(a128[strong, 8], 8 * a16[strong, 8], rtol=TOL, atol=0)
     assert np.abs(np.delete(a128, 8, axis=1)).max() <= 1e-6 * a128.max()
     rnd = synth.uniform_bytes(44, (2, 3, 384, 2048))
     f = synth.chan_freq_hz([10, 500, 1000])
