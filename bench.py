@@ -49,14 +49,11 @@ PEAK = {"fp32": (157.3, "TFLOP/s", "alu"),    # MI355X FP32 vector peak (publish
         "fp16": (2500.0, "TFLOP/s", "mfma"),  # MI355X dense FP16 matrix peak
         "fp32_mfma": (2500.0, "TFLOP/s", "mfma")}
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAME = {"fp32": "bf_fp32_kernel<true, false>", "fp16": "bf_mfma_kernel<2, false, false>",
-               "fp32_mfma": "bf_mfma_kernel<2, true, false>"}
+KERNEL_NAME = {"fp32": "bf_fp32_kernel<false>", "fp16": "bf_mfma_kernel<false, false>",
+               "fp32_mfma": "bf_mfma_kernel<true, false>"}
 # the 128-point up-channelisation (one pass)
 UPCHAN_KERNEL_NAME = {"fp32": "bf_fp32_up128_kernel<true>", "fp16": "bf_mfma_up128_kernel<2, false>",
                       "fp32_mfma": "bf_mfma_up128_kernel<2, true>"}
-# directions without mirror symmetry (tracking beams) take the general E-W form
-KERNEL_NAME_GENERAL = {"fp32": "bf_fp32_kernel<false, false>", "fp16": "bf_mfma_kernel<1, false, false>",
-                       "fp32_mfma": "bf_mfma_kernel<1, true, false>"}
 DTYPE = {"fp32": "f32", "fp16": "f16 x f16 -> f32 (MFMA)",
          "fp32_mfma": "f16 hi+lo pairs -> f32 (MFMA, FP32-class)"}
 PATH_NAME = {"fp32": "fp32_fft", "fp16": "fp16_mfma", "fp32_mfma": "fp32_mfma"}
@@ -225,7 +222,7 @@ def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None, u8=None, u
     flops = (FLOPS_PER_UNIT_128 if upchan == 128 else FLOPS_PER_UNIT)[prec] * units
     peak, punit, bound = PEAK[prec]
     achieved = flops / kern_s / 1e12
-    kernel = (KERNEL_NAME if sin_phi is None else KERNEL_NAME_GENERAL)[prec]
+    kernel = KERNEL_NAME[prec]  # every E-W geometry runs the same kernel
     traffic = None
     if sin_phi is None and not u8:
         traffic = traffic_from_profiles(prec, units, "upchan128_config1" if upchan == 128
