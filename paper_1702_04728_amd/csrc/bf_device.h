@@ -253,72 +253,8 @@ __device__ __forceinline__ void time_y_class(int s0, const uint2 (&raw)[16], uin
     }
 }
 
-// One 16-sample block of this thread's 8 inputs (bytes 8t .. 8t+7 of each
-// sample): time-DFT bins s = S0 + 4 s2, s2 = 0..3, by a radix-4 split of the
-// 16-point DFT:
-//   y[t1] = sum_t2 x[t1 + 4 t2] (-i)^(t2 S0)        (time_y)
-//   T[s2] = sum_t1 (y[t1] w16^(t1 S0)) (-i)^(t1 s2)
-// y is converted to float once.
-// Output: T[s2 * 1024 + tslot(slot)], slot = cyl * 256 + feed, float4 = both pols.
-template <int S0>
-__device__ __forceinline__ void time_dft(const uint2 (&raw)[16], float4* __restrict__ T, int t)
-{
-    uint32_t yr[4][2], yi[4][2];
-    time_y<S0>(raw, yr, yi);
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-        float2 o[2][4];
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int e = 2 * h + p;  // input 8t + e: feed 4 (t % 64) + h, pol p
-            const int w = e >> 2;
-            // each byte is value + 32 (both components); the exact subtraction
-            // keeps a zero-valued input exactly zero (class 0: the offset reaches
-            // only bin 0 and is removed there)
-            constexpr float kOff = S0 == 0 ? 0.f : 32.f;
-            float2 y[4];
-#pragma unroll
-            for (int t1 = 0; t1 < 4; ++t1)
-                y[t1] = make_float2(ubyte_to_float(yr[t1][w], e & 3) - kOff,
-                                    ubyte_to_float(yi[t1][w], e & 3) - kOff);
-            y[1] = tw16<S0>(y[1]);
-            y[2] = tw16<2 * S0>(y[2]);
-            y[3] = tw16<3 * S0>(y[3]);
-            dft4(y[0], y[1], y[2], y[3]);
-            if constexpr (S0 == 0) {
-                // no twiddles: the offset reaches only bin 0, as 4 x 32, and every
-                // value here is an integer far below 2^24, so this is exact
-                y[0] = make_float2(y[0].x - 128.f, y[0].y - 128.f);
-            }
-#pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2) o[p][s2] = y[s2];
-        }
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2)
-            T[s2 * 1024 + tslot(4 * t + h)] = make_float4(o[0][s2].x, o[0][s2].y, o[1][s2].x, o[1][s2].y);
-    }
-}
-
-__device__ __forceinline__ void time_dft_class(int s0, const uint2 (&raw)[16], float4* T, int t)
-{
-    switch (s0) {
-    case 0: time_dft<0>(raw, T, t); break;
-    case 1: time_dft<1>(raw, T, t); break;
-    case 2: time_dft<2>(raw, T, t); break;
-    default: time_dft<3>(raw, T, t); break;
-    }
-}
-
-// Raw samples of one block of 16: thread t reads bytes 8t .. 8t+7 of each
-// sample (64 lanes x 8 B contiguous per sample); rows `stride` bytes apart.
-__device__ __forceinline__ void load_block(const uint8_t* __restrict__ blk, uint2 (&raw)[16], int t,
-                                           int stride = kInputs)
-{
-#pragma unroll
-    for (int tau = 0; tau < 16; ++tau)
-        raw[tau] = *reinterpret_cast<const uint2*>(blk + tau * stride + 8 * t);
-}
-// The same with an arbitrary 8-byte-aligned offset into each sample row.
+// Raw samples of one block of 16: the 8 bytes at offset `off` (8-byte aligned)
+// of each sample row.
 __device__ __forceinline__ void load_block_at(const uint8_t* __restrict__ blk, uint2 (&raw)[16], int off)
 {
 #pragma unroll
