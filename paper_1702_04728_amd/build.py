@@ -20,6 +20,11 @@ HIP_FLAGS = [
 ]
 
 
+# roctx (API-call ranges for rocprofv3 --marker-trace)
+ROCM_LIB = "/opt/rocm/lib"
+LINK = ["-L" + ROCM_LIB, "-Wl,-rpath," + ROCM_LIB, "-lrocprofiler-sdk-roctx"]
+
+
 def sources():
     csrc = os.path.join(PKG, "csrc")
     return sorted(glob.glob(os.path.join(csrc, "*.cpp")) + glob.glob(os.path.join(csrc, "*.hip")))
@@ -55,7 +60,7 @@ def build(verbose: bool = False) -> str:
     if failed:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + LINK
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

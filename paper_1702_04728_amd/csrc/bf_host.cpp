@@ -21,6 +21,7 @@
 #include <string>
 
 #include "bf_plan.h"
+#include "bf_trace.h"
 
 namespace {
 
@@ -313,6 +314,7 @@ int32_t beamform_compute_lut(const bf_config* cfg, const double* chan_freq_hz, i
 int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t n_chan,
                       void* stream, bf_plan** out_plan)
 {
+    bf::TraceRange trace_range("beamform_init");
     g_init_error.clear();
     if (!out_plan) return fail(nullptr, BF_E_INVAL, "out_plan is NULL");
     if (!chan_freq_hz || n_chan <= 0) return fail(nullptr, BF_E_INVAL, "need n_chan > 0 frequencies");
@@ -411,6 +413,7 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
 int32_t beamform_frame(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float* d_out,
                        void* stream)
 {
+    bf::TraceRange trace_range("beamform_frame");
     if (!p) return BF_E_INVAL;
     p->err.clear();
     int32_t st = check_batch(p, d_in, n_frames, d_out);
@@ -422,6 +425,7 @@ int32_t beamform_frame_u8(bf_plan* p, const uint8_t* d_in, int32_t n_frames,
                           const float* d_scale, const float* d_offset, uint8_t* d_out,
                           void* stream)
 {
+    bf::TraceRange trace_range("beamform_frame_u8");
     if (!p) return BF_E_INVAL;
     p->err.clear();
     int32_t st = check_batch(p, d_in, n_frames, d_out);
@@ -436,6 +440,7 @@ int32_t beamform_frame_u8(bf_plan* p, const uint8_t* d_in, int32_t n_frames,
 int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_frames, float* d_out,
                                  void* stream)
 {
+    bf::TraceRange trace_range("beamform_frame_upchan128");
     if (!p) return BF_E_INVAL;
     p->err.clear();
     int32_t st = check_batch(p, d_in, n_frames, d_out);
@@ -466,6 +471,7 @@ int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_fram
 
 int32_t beamform_debug_ns(bf_plan* p, const uint8_t* d_in, float* d_ns_out, void* stream)
 {
+    bf::TraceRange trace_range("beamform_debug_ns");
     if (!p) return BF_E_INVAL;
     p->err.clear();
     int32_t st = check_batch(p, d_in, 1, d_ns_out);
@@ -493,6 +499,7 @@ int32_t beamform_debug_ns(bf_plan* p, const uint8_t* d_in, float* d_ns_out, void
 int32_t beamform_frame_tracking(bf_plan* p, const uint8_t* d_in, int32_t n_frames,
                                 const double* sin_phi_ew, float* d_out, void* stream)
 {
+    bf::TraceRange trace_range("beamform_frame_tracking");
     if (!p) return BF_E_INVAL;
     p->err.clear();
     int32_t st = check_batch(p, d_in, n_frames, d_out);
@@ -536,6 +543,7 @@ int32_t beamform_frame_tracking(bf_plan* p, const uint8_t* d_in, int32_t n_frame
 int32_t beamform_frame_tracking_noalloc(bf_plan* p, const uint8_t* d_in, int32_t n_frames,
                                         const double* sin_phi_ew, float* d_out, void* stream)
 {
+    bf::TraceRange trace_range("beamform_frame_tracking_noalloc");
     if (!p) return BF_E_INVAL;
     p->err.clear();
     int32_t st = check_batch(p, d_in, n_frames, d_out);
@@ -581,6 +589,7 @@ int32_t beamform_plan_info(const bf_plan* p, int32_t* n_chan, int32_t* n_time, i
 
 int32_t beamform_destroy(bf_plan* p)
 {
+    bf::TraceRange trace_range("beamform_destroy");
     if (!p) return BF_OK;
     int32_t st = BF_OK;
     int prev = -1;

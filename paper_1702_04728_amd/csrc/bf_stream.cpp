@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "bf_plan.h"
+#include "bf_trace.h"
 
 namespace {
 
@@ -231,6 +232,7 @@ int32_t beamform_stream_schedule(const bf_stream_desc* d, int64_t psb, int64_t c
 
 int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st, void* stream)
 {
+    bf::TraceRange trace_range("beamform_stream");
     if (!p || !st) return BF_E_INVAL;
     p->err.clear();
     std::string msg;

@@ -1,10 +1,12 @@
-// Stand-ins for the library's device-side launchers, so that its host-only code
-// (bf_host.cpp, bf_stream.cpp) links into a program without device code: the
-// sanitizer build of the C ABI harness, which calls only host-only entry points.
-// Each returns an error; none is reached by that harness.
+// Stand-ins for the library's device-side launchers (and its roctx ranges), so
+// that its host-only code (bf_host.cpp, bf_stream.cpp) links into a program
+// without device code: the sanitizer build of the C ABI harness, which calls
+// only host-only entry points.  Each launcher returns an error; none is
+// reached by that harness.
 #include <hip/hip_runtime.h>
 
 #include "../../paper_1702_04728_amd/csrc/bf_internal.h"
+#include "../../paper_1702_04728_amd/csrc/bf_trace.h"
 
 namespace bf {
 hipError_t launch_fp32(const LaunchArgs&, hipStream_t) { return hipErrorNoBinaryForGpu; }
@@ -15,6 +17,8 @@ hipError_t launch_stream_flags(const StreamState*, float*, uint8_t*, int, int, h
 {
     return hipErrorNoBinaryForGpu;
 }
+void trace_push(const char*) {}
+void trace_pop() {}
 hipError_t noalloc_scratch(int, float2** out)
 {
     *out = nullptr;
