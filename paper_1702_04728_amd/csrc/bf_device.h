@@ -86,21 +86,6 @@ __device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d)
     d = csub(t1, rot<1>(t3));
 }
 
-// Byte k (0..3, a compile-time constant after unrolling) of x as a float: one
-// v_cvt_f32_ubyteN.  Kept opaque so that a following exact "- 32.f" is not
-// turned into integer arithmetic (mask, subtract, convert: three instructions).
-__device__ __forceinline__ float ubyte_to_float(uint32_t x, int k)
-{
-    float r;
-    switch (k) {
-    case 0: asm("v_cvt_f32_ubyte0 %0, %1" : "=v"(r) : "v"(x)); break;
-    case 1: asm("v_cvt_f32_ubyte1 %0, %1" : "=v"(r) : "v"(x)); break;
-    case 2: asm("v_cvt_f32_ubyte2 %0, %1" : "=v"(r) : "v"(x)); break;
-    default: asm("v_cvt_f32_ubyte3 %0, %1" : "=v"(r) : "v"(x)); break;
-    }
-    return r;
-}
-
 // Orders LDS traffic between the lanes of one wavefront.
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -194,52 +179,54 @@ __device__ __forceinline__ uint32_t add3_u32(uint32_t a, uint32_t b, uint32_t c)
     return r;
 }
 
-// LDS position (in float4) of time-DFT slot sigma = cyl * 256 + feed: bits 4-5
-// are XORed into bits 0-1.  The time DFT writes slots 4 t + h (lane stride 4)
-// and E-W phasing reads 16 consecutive slots; with the swizzle both touch 16
-// distinct 16-byte bank groups per 16 lanes, without it the writes hit 4.
-__device__ __forceinline__ int tslot(int sigma) { return sigma ^ ((sigma >> 4) & 3); }
+// One word of class-S0 stride-4 sums: v[t2] holds 4 inputs' bytes (4+4-bit,
+// offset binary) of sample t1 + 4 t2 for a fixed t1;
+//   y = sum_t2 x[t1 + 4 t2] (-i)^(t2 S0)        (4-point DFT over the stride)
+// as bytewise integer sums biased so that no byte borrows: byte k of yr (yi)
+// is Re (Im) y + 32 of input k, in every class.
+template <int S0>
+__device__ __forceinline__ void stride_sum(const uint32_t (&v)[4], uint32_t& yr, uint32_t& yi)
+{
+    // nibble planes: r, m hold the 4 offset-binary nibbles (value + 8) as bytes
+    constexpr uint32_t kLo = 0x0f0f0f0fu;
+    constexpr uint32_t kBias = 0x20202020u;  // +32 per byte keeps differences >= 0
+    uint32_t r[4], m[4];
+#pragma unroll
+    for (int t2 = 0; t2 < 4; ++t2) {
+        r[t2] = (v[t2] >> 4) & kLo;
+        m[t2] = v[t2] & kLo;
+    }
+    // x_k = x[t1 + 4k]; y = sum_k x_k (-i)^(k S0), each byte = value + 32
+    if constexpr (S0 == 0) {
+        yr = r[0] + r[1] + r[2] + r[3];  // = sum(value) + 32
+        yi = m[0] + m[1] + m[2] + m[3];
+    } else if constexpr (S0 == 1) {  // x0 - i x1 - x2 + i x3
+        yr = add3_u32(r[0], m[1], kBias) - (r[2] + m[3]);
+        yi = add3_u32(m[0], r[3], kBias) - (r[1] + m[2]);
+    } else if constexpr (S0 == 2) {  // x0 - x1 + x2 - x3
+        yr = add3_u32(r[0], r[2], kBias) - (r[1] + r[3]);
+        yi = add3_u32(m[0], m[2], kBias) - (m[1] + m[3]);
+    } else {  // x0 + i x1 - x2 - i x3
+        yr = add3_u32(r[0], m[3], kBias) - (m[1] + r[2]);
+        yi = add3_u32(m[0], r[1], kBias) - (m[2] + r[3]);
+    }
+}
 
-// Integer part of the class-S0 time DFT of this thread's 8 inputs (bytes
-// 8t .. 8t+7 of each sample row, or whichever 8 consecutive bytes raw holds):
-//   y[t1] = sum_t2 x[t1 + 4 t2] (-i)^(t2 S0)        (4-point DFT over the stride)
-// formed on the raw nibbles four inputs at a time, as bytewise integer sums
-// in a 32-bit word biased so that no byte borrows: byte k of yr[t1][w]
-// (yi[t1][w]) is Re (Im) y[t1] + 32 of input 4 w + k, in every class.
+// Integer part of the class-S0 time DFT of this thread's 8 inputs (the 8
+// consecutive bytes raw holds of each of the 16 sample rows): byte k of
+// yr[t1][w] (yi[t1][w]) is Re (Im) y[t1] + 32 of input 4 w + k (stride_sum).
 template <int S0>
 __device__ __forceinline__ void time_y(const uint2 (&raw)[16], uint32_t (&yr)[4][2], uint32_t (&yi)[4][2])
 {
-    // nibble planes: r, m hold the 4 offset-binary nibbles (value + 8) of
-    // inputs 4w .. 4w + 3 as bytes
-    constexpr uint32_t kLo = 0x0f0f0f0fu;
-    constexpr uint32_t kBias = 0x20202020u;  // +32 per byte keeps differences >= 0
 #pragma unroll
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < 2; ++w)
 #pragma unroll
         for (int t1 = 0; t1 < 4; ++t1) {
-            uint32_t r[4], m[4];
+            uint32_t v[4];
 #pragma unroll
-            for (int t2 = 0; t2 < 4; ++t2) {
-                const uint32_t v = w ? raw[t1 + 4 * t2].y : raw[t1 + 4 * t2].x;
-                r[t2] = (v >> 4) & kLo;
-                m[t2] = v & kLo;
-            }
-            // x_k = x[t1 + 4k]; y = sum_k x_k (-i)^(k S0), each byte = value + 32
-            if constexpr (S0 == 0) {
-                yr[t1][w] = r[0] + r[1] + r[2] + r[3];  // = sum(value) + 32
-                yi[t1][w] = m[0] + m[1] + m[2] + m[3];
-            } else if constexpr (S0 == 1) {  // x0 - i x1 - x2 + i x3
-                yr[t1][w] = add3_u32(r[0], m[1], kBias) - (r[2] + m[3]);
-                yi[t1][w] = add3_u32(m[0], r[3], kBias) - (r[1] + m[2]);
-            } else if constexpr (S0 == 2) {  // x0 - x1 + x2 - x3
-                yr[t1][w] = add3_u32(r[0], r[2], kBias) - (r[1] + r[3]);
-                yi[t1][w] = add3_u32(m[0], m[2], kBias) - (m[1] + m[3]);
-            } else {  // x0 + i x1 - x2 - i x3
-                yr[t1][w] = add3_u32(r[0], m[3], kBias) - (m[1] + r[2]);
-                yi[t1][w] = add3_u32(m[0], r[1], kBias) - (m[2] + r[3]);
-            }
+            for (int t2 = 0; t2 < 4; ++t2) v[t2] = w ? raw[t1 + 4 * t2].y : raw[t1 + 4 * t2].x;
+            stride_sum<S0>(v, yr[t1][w], yi[t1][w]);
         }
-    }
 }
 
 __device__ __forceinline__ void time_y_class(int s0, const uint2 (&raw)[16], uint32_t (&yr)[4][2],
@@ -357,21 +344,27 @@ __device__ __forceinline__ void load_ew_mats(const float2* __restrict__ ew_row, 
     }
 }
 
-// A fragment of input 4 wd + m of this lane (K = (t1, re/im) of its
-// cylinder): y[t1] exactly, from the biased bytes of time_y.  One byte
-// permute places Re and Im of one t1 into the low bytes of two halves, the
-// exponent bits of 1024 make each half 1024 + byte, and one packed FP16
-// subtraction of 1024 + 32 leaves y.
-__device__ __forceinline__ half8 y_fragment(const uint32_t (&yr)[4][2], const uint32_t (&yi)[4][2], int wd,
-                                            int m)
+// A fragment of input m of one word column (K = (t1, re/im)): y[t1] exactly,
+// from the biased bytes of stride_sum.  One byte permute places Re and Im of
+// one t1 in the low bytes of two halves, the exponent bits of 1024 make each
+// half 1024 + byte, and one packed FP16 subtraction of 1024 + 32 leaves y.
+__device__ __forceinline__ half8 y_fragment1(const uint32_t (&yr)[4], const uint32_t (&yi)[4], int m)
 {
     const uint32_t sel = 0x0c000c00u | ((4u + m) << 16) | (uint32_t)m;  // (yr byte m, 0, yi byte m, 0)
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     u32x4 d;
 #pragma unroll
-    for (int t1 = 0; t1 < 4; ++t1) d[t1] = __builtin_amdgcn_perm(yi[t1][wd], yr[t1][wd], sel) | 0x64006400u;
+    for (int t1 = 0; t1 < 4; ++t1) d[t1] = __builtin_amdgcn_perm(yi[t1], yr[t1], sel) | 0x64006400u;
     const half8 bias = {1056.f16, 1056.f16, 1056.f16, 1056.f16, 1056.f16, 1056.f16, 1056.f16, 1056.f16};
     return __builtin_bit_cast(half8, d) - bias;
+}
+// The same for input 4 wd + m of time_y's two word columns.
+__device__ __forceinline__ half8 y_fragment(const uint32_t (&yr)[4][2], const uint32_t (&yi)[4][2], int wd,
+                                            int m)
+{
+    const uint32_t r[4] = {yr[0][wd], yr[1][wd], yr[2][wd], yr[3][wd]};
+    const uint32_t i[4] = {yi[0][wd], yi[1][wd], yi[2][wd], yi[3][wd]};
+    return y_fragment1(r, i, m);
 }
 
 // One tile of the fused time-DFT tail + E-W product: input e (0..7) of every
@@ -443,40 +436,10 @@ __device__ __forceinline__ int r128_for(int k, int q)
 // Sub-channel integrated by wave w of a workgroup of parity par.
 __device__ __forceinline__ int q128_of_wave(int par, int w) { return (2 * w + 8 + par) & 15; }
 
-// In-place DFT-8, natural order: X_r = sum_u x_u w8^(r u).
-__device__ __forceinline__ void dft8(float2 (&x)[8])
-{
-    float2 e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
-    float2 o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
-    dft4(e0, e1, e2, e3);
-    dft4(o0, o1, o2, o3);
-    // w8^1 = (1 - i)/sqrt2, w8^2 = -i, w8^3 = -(1 + i)/sqrt2
-    o1 = make_float2((o1.x + o1.y) * kR2, (o1.y - o1.x) * kR2);
-    o2 = rot<1>(o2);
-    o3 = make_float2((o3.y - o3.x) * kR2, -(o3.x + o3.y) * kR2);
-    x[0] = cadd(e0, o0);
-    x[4] = csub(e0, o0);
-    x[1] = cadd(e1, o1);
-    x[5] = csub(e1, o1);
-    x[2] = cadd(e2, o2);
-    x[6] = csub(e2, o2);
-    x[3] = cadd(e3, o3);
-    x[7] = csub(e3, o3);
-}
-
-// Bin k (class S0 = k mod 4) of the 128-point DFT of one 128-sample block for
-// this thread's 4 inputs (bytes 4t .. 4t+3 of each sample row: feeds 2t, 2t+1
-// of one cylinder, both pols): the 8 fine slices r go to T[r * 1024 +
-// tslot(slot)], float4 = both pols, slot = cyl * 256 + feed = 2t, 2t + 1.
-//   y_u[t1] = sum_t2 x[u + 8 (t1 + 4 t2)] (-i)^(S0 t2)    (bytewise integer sums)
-//   Z_u     = w128^(u k) Y_u[k] = sum_t1 w128^(k (u + 8 t1)) y_u[t1]
-//   X[r]    = DFT-8 over u of Z_u
-// twk[m] = w128^(k m), m < 32 (host FP64, rounded once).  Every converted
-// value has its bias taken off exactly, so a zero-valued input stays zero.
 // The unit's samples are read through a buffer resource (base and size in
 // SGPRs, bounds-checked by the hardware: reads past `bytes` return 0): one
 // VGPR lane offset and scalar row offsets, where 64-bit per-row addresses
-// would hold 32 VGPRs.
+// would hold many VGPRs.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t unit_rsrc(const uint8_t* base, int bytes)
 {
     // dword 3 of a raw (untyped) buffer descriptor on gfx9-family GPUs
@@ -487,105 +450,78 @@ __device__ __forceinline__ uint32_t load_word(__amdgpu_buffer_rsrc_t r, int lane
     return __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, row_off, 0);
 }
 
-// This thread's words of sample phase u = 0 of a 128-sample block (the same for
-// every bin k of the block: loaded once per block, ahead of use).
-__device__ __forceinline__ void load_phase0(__amdgpu_buffer_rsrc_t src, int blk_off, int t,
-                                            uint32_t (&w)[16])
-{
-#pragma unroll
-    for (int tau = 0; tau < 16; ++tau) w[tau] = load_word(src, 4 * t, blk_off + 8 * tau * kInputs);
-}
+// Float4 per fine slice in LDS: 1024 slots (slot = cyl * 256 + feed, float4 =
+// both pols) and 1 of padding, so that the eight slices' writes of one
+// instruction fall on different banks.
+constexpr int kSlice128 = 1025;
 
+// Bin k (class S0 = k mod 4) of the 128-point DFT of one 128-sample block for
+// all 2048 inputs: the 8 fine slices r go to T[(r * kSlice128 + slot) * 4 +
+// 2 pol + re/im].  With t = u + 8 t1 + 32 t2 within the block,
+//   y_u[t1]    = sum_t2 x[t] (-i)^(S0 t2)      (exact integers, stride_sum)
+//   X[k + 16r] = sum_(u, t1) w128^(k (u + 8 t1)) w8^(r u) y_u[t1],
+// the second a real 64 x 16 matrix per bin on the matrix cores (two K-steps of
+// 32, kappa = u div 4; FP16 hi + lo matrix Bk in fragment order, exact FP16
+// operands, FP32 results).  Wave w takes inputs 256 w .. 256 w + 255 as four
+// sets of 64: lane (g, rr) reads word column D = 64 w + 16 m + rr (inputs
+// 4 D .. 4 D + 3) of sample phases u = g and 4 + g, forms their stride sums,
+// and holds row rr of tile e (input 4 D + e) for K-step kappa = u div 4.  A
+// zero-valued input stays exactly zero.
 template <int S0>
 __device__ __forceinline__ void time_dft128(__amdgpu_buffer_rsrc_t src, int blk_off,
-                                            const uint32_t (&phase0)[16],
-                                            const float2* __restrict__ twk,
-                                            float4* __restrict__ T, int t)
+                                            const half8* __restrict__ Bk, float* __restrict__ T, int t)
 {
-    constexpr uint32_t kLo = 0x0f0f0f0fu;
-    constexpr uint32_t kBias = 0x20202020u;
-    float2 Z[8][4];  // [u][input byte e]
-    uint32_t raw[16], nxt[16];
+    const int lane = t & 63, w = t >> 6, g = lane >> 4, rr = lane & 15;
+    const half8 B0h = Bk[0 * 64 + lane], B0l = Bk[1 * 64 + lane];
+    const half8 B1h = Bk[2 * 64 + lane], B1l = Bk[3 * 64 + lane];
+    // output column of this lane: slice r = rr mod 8, real (nu = 0) or imaginary
+    // part; its stores are this base plus compile-time offsets
+    float* const Tl = T + (((rr & 7) * kSlice128 + 128 * w + 8 * g) * 4 + (rr >> 3));
+    // this lane's sample phase g (+ 4 kappa) row and word column, in bytes;
+    // the rest of each row offset is uniform (scalar)
+    const int lane_off = g * kInputs + 4 * (64 * w + rr);
 #pragma unroll
-    for (int tau = 0; tau < 16; ++tau) nxt[tau] = phase0[tau];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        // one phase u at a time: without the barrier the scheduler hoists every
-        // phase's loads and runs out of registers
+    for (int m = 0; m < 4; ++m) {
+        // one set at a time: without the barrier the scheduler hoists every
+        // set's loads and runs out of registers
         __builtin_amdgcn_sched_barrier(0);
+        uint32_t yr[2][4], yi[2][4];
 #pragma unroll
-        for (int tau = 0; tau < 16; ++tau) raw[tau] = nxt[tau];
-        if (u < 7) {
+        for (int kap = 0; kap < 2; ++kap) {
+            uint32_t raw[16];
 #pragma unroll
             for (int tau = 0; tau < 16; ++tau)
-                nxt[tau] = load_word(src, 4 * t, blk_off + (u + 1 + 8 * tau) * kInputs);
-        }
-        uint32_t yr[4], yi[4];
+                raw[tau] = load_word(src, lane_off + 64 * m, blk_off + (4 * kap + 8 * tau) * kInputs);
 #pragma unroll
-        for (int t1 = 0; t1 < 4; ++t1) {
-            uint32_t r[4], m[4];
-#pragma unroll
-            for (int t2 = 0; t2 < 4; ++t2) {
-                const uint32_t v = raw[t1 + 4 * t2];
-                r[t2] = (v >> 4) & kLo;
-                m[t2] = v & kLo;
-            }
-            // each byte of y = value + 32 (both components)
-            if constexpr (S0 == 0) {
-                yr[t1] = r[0] + r[1] + r[2] + r[3];
-                yi[t1] = m[0] + m[1] + m[2] + m[3];
-            } else if constexpr (S0 == 1) {  // x0 - i x1 - x2 + i x3
-                yr[t1] = add3_u32(r[0], m[1], kBias) - (r[2] + m[3]);
-                yi[t1] = add3_u32(m[0], r[3], kBias) - (r[1] + m[2]);
-            } else if constexpr (S0 == 2) {  // x0 - x1 + x2 - x3
-                yr[t1] = add3_u32(r[0], r[2], kBias) - (r[1] + r[3]);
-                yi[t1] = add3_u32(m[0], m[2], kBias) - (m[1] + m[3]);
-            } else {  // x0 + i x1 - x2 - i x3
-                yr[t1] = add3_u32(r[0], m[3], kBias) - (m[1] + r[2]);
-                yi[t1] = add3_u32(m[0], r[1], kBias) - (m[2] + r[3]);
+            for (int t1 = 0; t1 < 4; ++t1) {
+                const uint32_t v[4] = {raw[t1], raw[t1 + 4], raw[t1 + 8], raw[t1 + 12]};
+                stride_sum<S0>(v, yr[kap][t1], yi[kap][t1]);
             }
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            float2 acc = make_float2(0.f, 0.f);
+            const half8 A0 = y_fragment1(yr[0], yi[0], e), A1 = y_fragment1(yr[1], yi[1], e);
+            const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+            floatx4 X = mfma16(A0, B0h, zero);
+            X = mfma16(A0, B0l, X);
+            X = mfma16(A1, B1h, X);
+            X = mfma16(A1, B1l, X);
+            // row 4 g + i: input 4 (64 w + 16 m + 4 g + i) + e, i.e. slot
+            // 2 (64 w + 16 m + 4 g + i) + (e >> 1), pol e & 1
 #pragma unroll
-            for (int t1 = 0; t1 < 4; ++t1) {
-                const float2 y = make_float2(ubyte_to_float(yr[t1], e) - 32.f,
-                                             ubyte_to_float(yi[t1], e) - 32.f);
-                const float2 w = twk[u + 8 * t1];
-                acc = t1 == 0 ? cmul(y, w) : cmac(acc, y, w);
-            }
-            // pins the phase's arithmetic here: otherwise the compiler defers it
-            // to the end and keeps every phase's converted values live instead
-            asm volatile("" : "+v"(acc.x), "+v"(acc.y));
-            Z[u][e] = acc;
+            for (int i = 0; i < 4; ++i) Tl[(32 * m + 2 * i + (e >> 1)) * 4 + 2 * (e & 1)] = X[i];
         }
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        float2 x[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = Z[u][e];
-        dft8(x);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) Z[u][e] = x[u];  // Z[r][e] from here on
-    }
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        T[r * 1024 + tslot(2 * t)] = make_float4(Z[r][0].x, Z[r][0].y, Z[r][1].x, Z[r][1].y);
-        T[r * 1024 + tslot(2 * t + 1)] = make_float4(Z[r][2].x, Z[r][2].y, Z[r][3].x, Z[r][3].y);
     }
 }
 
 __device__ __forceinline__ void time_dft128_bin(int k, __amdgpu_buffer_rsrc_t src, int blk_off,
-                                                const uint32_t (&phase0)[16], const float2* twk,
-                                                float4* T, int t)
+                                                const half8* Bk, float* T, int t)
 {
     switch (k & 3) {
-    case 0: time_dft128<0>(src, blk_off, phase0, twk, T, t); break;
-    case 1: time_dft128<1>(src, blk_off, phase0, twk, T, t); break;
-    case 2: time_dft128<2>(src, blk_off, phase0, twk, T, t); break;
-    default: time_dft128<3>(src, blk_off, phase0, twk, T, t); break;
+    case 0: time_dft128<0>(src, blk_off, Bk, T, t); break;
+    case 1: time_dft128<1>(src, blk_off, Bk, T, t); break;
+    case 2: time_dft128<2>(src, blk_off, Bk, T, t); break;
+    default: time_dft128<3>(src, blk_off, Bk, T, t); break;
     }
 }
 

@@ -223,7 +223,7 @@ __device__ __forceinline__ void ew_group(const float2* __restrict__ Tp, const fl
     for (int aa = 0; aa < 16; ++aa) {
         float2 y[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) y[c] = Tp[2 * tslot(c * 256 + 16 * aa + b)];
+        for (int c = 0; c < 4; ++c) y[c] = Tp[2 * (c * 256 + 16 * aa + b)];
         if constexpr (kSym) {
             const float2 S0 = cadd(y[0], y[3]), S1 = cadd(y[1], y[2]);
             const float2 D0 = csub(y[0], y[3]), D1 = csub(y[1], y[2]);
@@ -398,7 +398,7 @@ void bf_fp32_kernel(LaunchArgs a)
 // (128 KB in LDS), wave w's groups take the slice whose fine channel lands in
 // its sub-channel through E-W phasing and the N-S transform into |X|^2 per bin.
 constexpr int kUnion128F2 = 32 * kGroupF2;       // 32 groups' transposes (17,920 float2)
-static_assert(kUnion128F2 * 8 >= 8 * 1024 * 16, "union region must hold the 8 fine slices");
+static_assert(kUnion128F2 * 8 >= 8 * kSlice128 * 16, "union region must hold the 8 fine slices");
 static_assert(kUnion128F2 * 8 >= 8 * 4 * 512 * 4, "union region must hold the per-bin powers");
 
 template <bool kSym>
@@ -431,7 +431,6 @@ void bf_fp32_up128_kernel(LaunchArgs a)
 
     const __amdgpu_buffer_rsrc_t src = unit_rsrc(a.in + (size_t)wk.unit * a.n_time * kInputs,
                                                  a.n_time * kInputs);
-    float4* T = reinterpret_cast<float4*>(s_union);
     const float2* Tp = reinterpret_cast<const float2*>(s_union) + pol;
     float2* bufE = s_union + g * kGroupF2;
     float2* bufO = bufE + kXpBuf;
@@ -444,16 +443,15 @@ void bf_fp32_up128_kernel(LaunchArgs a)
         for (int d = 0; d < 16; ++d) acc[l][0][d] = acc[l][1][d] = 0.f;
 
     const int n_blk128 = a.n_time / 128;
-    uint32_t phase0[16];  // the block's first sample phase, loaded a block ahead
-    load_phase0(src, 0, t, phase0);
+    const half8* mf128 = reinterpret_cast<const half8*>(a.mf128);
     for (int blk = 0; blk < n_blk128; ++blk) {
         for (int i = 0; i < 8; ++i) {
             const int k = k128_of(wk.par, i);
-            time_dft128_bin(k, src, blk * 128 * kInputs, phase0, a.tw128k + k * 32, T, t);
-            if (i == 7 && blk + 1 < n_blk128) load_phase0(src, (blk + 1) * 128 * kInputs, t, phase0);
+            time_dft128_bin(k, src, blk * 128 * kInputs, mf128 + k * 4 * 64,
+                            reinterpret_cast<float*>(s_union), t);
             __syncthreads();
             float2 v0[16], v1[16];
-            ew_group<kSym>(Tp + 2 * r128_for(k, qw) * 1024, W, v0, v1, b);
+            ew_group<kSym>(Tp + 2 * r128_for(k, qw) * kSlice128, W, v0, v1, b);
             __syncthreads();
             ns_line_power<false>(v0, acc[0], bufE, bufO, s_tw, b, lv, nullptr);
             ns_line_power<false>(v1, acc[1], bufE, bufO, s_tw, b, lv, nullptr);

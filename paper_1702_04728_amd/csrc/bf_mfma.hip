@@ -175,7 +175,7 @@ __device__ __forceinline__ void ew_fragments(const float4* __restrict__ Ts, cons
             float2 y0[4], y1[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const float4 x4 = Ts[tslot(c * 256 + 16 * (4 * q + ia) + n)];
+                const float4 x4 = Ts[c * 256 + 16 * (4 * q + ia) + n];
                 y0[c] = make_float2(x4.x, x4.y);
                 y1[c] = make_float2(x4.z, x4.w);
             }
@@ -198,7 +198,7 @@ __device__ __forceinline__ void ew_fragments(const float4* __restrict__ Ts, cons
                 float2 y[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const float4 x4 = Ts[tslot(c * 256 + 16 * (4 * q + ia) + n)];
+                    const float4 x4 = Ts[c * 256 + 16 * (4 * q + ia) + n];
                     y[c] = p ? make_float2(x4.z, x4.w) : make_float2(x4.x, x4.y);
                 }
                 ew_phase<kEw>(y, W, v, ia);
@@ -438,7 +438,7 @@ template <int kEw, bool kSplitV>
 __global__ __launch_bounds__(kThreads128) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bf_mfma_up128_kernel(LaunchArgs a)
 {
-    __shared__ __align__(16) float4 s_T[8 * 1024];  // 8 fine slices, then per-bin powers
+    __shared__ __align__(16) float4 s_T[8 * kSlice128];  // 8 fine slices, then per-bin powers
 
     const Work128 wk = work128_of_block();
     if (wk.unit >= a.n_units) return;  // uniform across the workgroup
@@ -466,17 +466,16 @@ void bf_mfma_up128_kernel(LaunchArgs a)
             for (int i = 0; i < 4; ++i) acc[j][nu][i] = 0.f;
 
     const int n_blk128 = a.n_time / 128;
-    uint32_t phase0[16];  // the block's first sample phase, loaded a block ahead
-    load_phase0(src, 0, t, phase0);
+    const half8* mf128 = reinterpret_cast<const half8*>(a.mf128);
     for (int blk = 0; blk < n_blk128; ++blk) {
         for (int i = 0; i < 8; ++i) {
             const int k = k128_of(wk.par, i);
-            time_dft128_bin(k, src, blk * 128 * kInputs, phase0, a.tw128k + k * 32, s_T, t);
-            if (i == 7 && blk + 1 < n_blk128) load_phase0(src, (blk + 1) * 128 * kInputs, t, phase0);
+            time_dft128_bin(k, src, blk * 128 * kInputs, mf128 + k * 4 * 64,
+                            reinterpret_cast<float*>(s_T), t);
             __syncthreads();
             half8 A[4][2];
             [[maybe_unused]] half8 Alo[4][2];
-            ew_fragments<kEw, kSplitV>(s_T + r128_for(k, qw) * 1024, W, A, Alo, q, n);
+            ew_fragments<kEw, kSplitV>(s_T + r128_for(k, qw) * kSlice128, W, A, Alo, q, n);
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < 4; ++j)
