@@ -445,9 +445,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t unit_rsrc(const uint8_t* base,
     // dword 3 of a raw (untyped) buffer descriptor on gfx9-family GPUs
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), 0, bytes, 0x00020000);
 }
-__device__ __forceinline__ uint32_t load_word(__amdgpu_buffer_rsrc_t r, int lane_off, int row_off)
+__device__ __forceinline__ uint2 load_pair(__amdgpu_buffer_rsrc_t r, int lane_off, int row_off)
 {
-    return __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, row_off, 0);
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, row_off, 0);
+    return make_uint2(v[0], v[1]);
 }
 
 // Float4 per fine slice in LDS: 1024 slots (slot = cyl * 256 + feed, float4 =
@@ -461,67 +463,89 @@ constexpr int kSlice128 = 1025;
 //   y_u[t1]    = sum_t2 x[t] (-i)^(S0 t2)      (exact integers, stride_sum)
 //   X[k + 16r] = sum_(u, t1) w128^(k (u + 8 t1)) w8^(r u) y_u[t1],
 // the second a real 64 x 16 matrix per bin on the matrix cores (two K-steps of
-// 32, kappa = u div 4; FP16 hi + lo matrix Bk in fragment order, exact FP16
-// operands, FP32 results).  Wave w takes inputs 256 w .. 256 w + 255 as four
-// sets of 64: lane (g, rr) reads word column D = 64 w + 16 m + rr (inputs
-// 4 D .. 4 D + 3) of sample phases u = g and 4 + g, forms their stride sums,
-// and holds row rr of tile e (input 4 D + e) for K-step kappa = u div 4.  A
+// 32, kappa = u div 4; exact FP16 operands, FP32 results).  Each matrix entry
+// is the single power w128^(k (u + 8 t1) + 16 r u) (w8 = w128^16), read from
+// w128[] (FP32, LDS) and split into FP16 hi + lo in the lane that holds it
+// (lane (g, n): K = (u = 4 kappa + g, t1, re/im), column n = slice r = n mod 8
+// of the real (n < 8) or imaginary output part): formed per bin in the
+// kernel, no table of per-bin matrices competes with the sample block for L2.  Wave w takes inputs 256 w .. 256 w + 255 as two
+// sets of 128: lane (g, rr) reads the 8 bytes (inputs) at word column
+// 64 w + 32 m + 2 rr of sample phases u = g and 4 + g (16 lanes: one whole
+// 128-byte line of a row per load), forms their stride sums, and holds row rr
+// of tile e (input 4 (64 w + 32 m + 2 rr) + e) for K-step kappa = u div 4.  A
 // zero-valued input stays exactly zero.
 template <int S0>
-__device__ __forceinline__ void time_dft128(__amdgpu_buffer_rsrc_t src, int blk_off,
-                                            const half8* __restrict__ Bk, float* __restrict__ T, int t)
+__device__ __forceinline__ void time_dft128(int k, __amdgpu_buffer_rsrc_t src, int blk_off,
+                                            const float2* __restrict__ w128, float* __restrict__ T, int t)
 {
     const int lane = t & 63, w = t >> 6, g = lane >> 4, rr = lane & 15;
-    const half8 B0h = Bk[0 * 64 + lane], B0l = Bk[1 * 64 + lane];
-    const half8 B1h = Bk[2 * 64 + lane], B1l = Bk[3 * 64 + lane];
+    half8 Bh[2], Bl[2];
+#pragma unroll
+    for (int kap = 0; kap < 2; ++kap) {
+        const int u = 4 * kap + g, r = rr & 7;
+#pragma unroll
+        for (int t1 = 0; t1 < 4; ++t1) {
+            const float2 mv = w128[(k * (u + 8 * t1) + 16 * r * u) & 127];
+            // real output: Re y Re M - Im y Im M; imaginary: Re y Im M + Im y Re M
+            float x[2] = {rr < 8 ? mv.x : mv.y, rr < 8 ? -mv.y : mv.x};
+#pragma unroll
+            for (int ri = 0; ri < 2; ++ri) {
+                // one FP32 value per entry, split once (see load_ew_mats)
+                asm volatile("" : "+v"(x[ri]));
+                const _Float16 hi = (_Float16)x[ri];
+                Bh[kap][2 * t1 + ri] = hi;
+                Bl[kap][2 * t1 + ri] = (_Float16)(x[ri] - (float)hi);
+            }
+        }
+    }
+    const half8 B0h = Bh[0], B0l = Bl[0], B1h = Bh[1], B1l = Bl[1];
     // output column of this lane: slice r = rr mod 8, real (nu = 0) or imaginary
     // part; its stores are this base plus compile-time offsets
-    float* const Tl = T + (((rr & 7) * kSlice128 + 128 * w + 8 * g) * 4 + (rr >> 3));
-    // this lane's sample phase g (+ 4 kappa) row and word column, in bytes;
+    float* const Tl = T + (((rr & 7) * kSlice128 + 128 * w + 16 * g) * 4 + (rr >> 3));
+    // this lane's sample phase g (+ 4 kappa) row and word columns, in bytes;
     // the rest of each row offset is uniform (scalar)
-    const int lane_off = g * kInputs + 4 * (64 * w + rr);
+    const int lane_off = g * kInputs + 4 * (64 * w + 2 * rr);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < 2; ++m) {
         // one set at a time: without the barrier the scheduler hoists every
         // set's loads and runs out of registers
         __builtin_amdgcn_sched_barrier(0);
-        uint32_t yr[2][4], yi[2][4];
+        uint32_t yr[2][4][2], yi[2][4][2];
 #pragma unroll
         for (int kap = 0; kap < 2; ++kap) {
-            uint32_t raw[16];
+            uint2 raw[16];
 #pragma unroll
             for (int tau = 0; tau < 16; ++tau)
-                raw[tau] = load_word(src, lane_off + 64 * m, blk_off + (4 * kap + 8 * tau) * kInputs);
-#pragma unroll
-            for (int t1 = 0; t1 < 4; ++t1) {
-                const uint32_t v[4] = {raw[t1], raw[t1 + 4], raw[t1 + 8], raw[t1 + 12]};
-                stride_sum<S0>(v, yr[kap][t1], yi[kap][t1]);
-            }
+                raw[tau] = load_pair(src, lane_off + 128 * m, blk_off + (4 * kap + 8 * tau) * kInputs);
+            time_y<S0>(raw, yr[kap], yi[kap]);
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const half8 A0 = y_fragment1(yr[0], yi[0], e), A1 = y_fragment1(yr[1], yi[1], e);
+        for (int e = 0; e < 8; ++e) {
+            const half8 A0 = y_fragment(yr[0], yi[0], e >> 2, e & 3);
+            const half8 A1 = y_fragment(yr[1], yi[1], e >> 2, e & 3);
             const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
             floatx4 X = mfma16(A0, B0h, zero);
             X = mfma16(A0, B0l, X);
             X = mfma16(A1, B1h, X);
             X = mfma16(A1, B1l, X);
-            // row 4 g + i: input 4 (64 w + 16 m + 4 g + i) + e, i.e. slot
-            // 2 (64 w + 16 m + 4 g + i) + (e >> 1), pol e & 1
+            // row 4 g + i: input 4 (64 w + 32 m + 8 g + 2 i + (e >> 2)) + (e & 3),
+            // i.e. slot 2 (64 w + 32 m + 8 g + 2 i + (e >> 2)) + ((e & 3) >> 1),
+            // pol e & 1
 #pragma unroll
-            for (int i = 0; i < 4; ++i) Tl[(32 * m + 2 * i + (e >> 1)) * 4 + 2 * (e & 1)] = X[i];
+            for (int i = 0; i < 4; ++i)
+                Tl[(64 * m + 4 * i + 2 * (e >> 2) + ((e & 3) >> 1)) * 4 + 2 * (e & 1)] = X[i];
         }
     }
 }
 
 __device__ __forceinline__ void time_dft128_bin(int k, __amdgpu_buffer_rsrc_t src, int blk_off,
-                                                const half8* Bk, float* T, int t)
+                                                const float2* w128, float* T, int t)
 {
     switch (k & 3) {
-    case 0: time_dft128<0>(src, blk_off, Bk, T, t); break;
-    case 1: time_dft128<1>(src, blk_off, Bk, T, t); break;
-    case 2: time_dft128<2>(src, blk_off, Bk, T, t); break;
-    default: time_dft128<3>(src, blk_off, Bk, T, t); break;
+    case 0: time_dft128<0>(k, src, blk_off, w128, T, t); break;
+    case 1: time_dft128<1>(k, src, blk_off, w128, T, t); break;
+    case 2: time_dft128<2>(k, src, blk_off, w128, T, t); break;
+    default: time_dft128<3>(k, src, blk_off, w128, T, t); break;
     }
 }
 

@@ -407,6 +407,7 @@ void bf_fp32_up128_kernel(LaunchArgs a)
 {
     __shared__ __align__(16) float2 s_union[kUnion128F2];
     __shared__ __align__(16) float4 s_tw[16 * 16];  // [c'][b]: w512^(b 2c'), w512^(b (2c'+1))
+    __shared__ __align__(16) float2 s_w128[128];    // w128^m
 
     const Work128 wk = work128_of_block();
     if (wk.unit >= a.n_units) return;  // uniform across the workgroup
@@ -443,11 +444,12 @@ void bf_fp32_up128_kernel(LaunchArgs a)
         for (int d = 0; d < 16; ++d) acc[l][0][d] = acc[l][1][d] = 0.f;
 
     const int n_blk128 = a.n_time / 128;
-    const half8* mf128 = reinterpret_cast<const half8*>(a.mf128);
+    if (t < 128) s_w128[t] = a.tw128[t];
+    __syncthreads();
     for (int blk = 0; blk < n_blk128; ++blk) {
         for (int i = 0; i < 8; ++i) {
             const int k = k128_of(wk.par, i);
-            time_dft128_bin(k, src, blk * 128 * kInputs, mf128 + k * 4 * 64,
+            time_dft128_bin(k, src, blk * 128 * kInputs, s_w128,
                             reinterpret_cast<float*>(s_union), t);
             __syncthreads();
             float2 v0[16], v1[16];

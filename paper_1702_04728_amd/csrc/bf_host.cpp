@@ -277,37 +277,6 @@ void build_mfma_tables(void* host_buf)
         }
 }
 
-// 128-point up-channelisation, bin k: with t = u + 8 t1 + 32 t2 within a
-// 128-sample block and y_u[t1] = sum_t2 x[t] (-i)^(k t2) (the exact integer
-// stride sums of class k mod 4), fine slice r of bin k is
-//   X[k + 16 r] = sum_(u, t1) w128^(k (u + 8 t1)) w8^(r u) y_u[t1],
-// one real 64 x 16 matrix per bin (K = (u, t1, re/im), columns (r, re/im)),
-// applied as two K-steps of v_mfma_f32_16x16x32_f16.  Fragments of bin k:
-// [k][kappa][hi, lo][lane][8 halves], lane (g, n): K-step kappa covers
-// u = 4 kappa + g, element i = 2 t1 + re/im; column n = slice r = n mod 8 of
-// the real (n < 8) or imaginary (n >= 8) output part.  FP64, split into FP16
-// hi + lo.
-void build_up128_tables(_Float16* h)
-{
-    for (int k = 0; k < 16; ++k)
-        for (int kap = 0; kap < 2; ++kap)
-            for (int lane = 0; lane < 64; ++lane)
-                for (int i = 0; i < 8; ++i) {
-                    const int g = lane >> 4, n = lane & 15;
-                    const int u = 4 * kap + g, t1 = i >> 1, ri = i & 1, r = n & 7, nu = n >> 3;
-                    const int ph128 = (k * (u + 8 * t1) + 16 * r * u) % 128;  // w8^(r u) = w128^(16 r u)
-                    const double a = kTwoPi * (double)ph128 / 128.0;
-                    const double mr = std::cos(a), mi = -std::sin(a);
-                    // real output: Re y mr - Im y mi; imaginary output: Re y mi + Im y mr
-                    const double v = nu == 0 ? (ri == 0 ? mr : -mi) : (ri == 0 ? mi : mr);
-                    const _Float16 hi = (_Float16)v;
-                    const _Float16 lo = (_Float16)(v - (double)hi);
-                    const size_t base = ((size_t)(k * 2 + kap) * 2) * 64;
-                    h[((base + 0 * 64 + lane) * 8) + i] = hi;
-                    h[((base + 1 * 64 + lane) * 8) + i] = lo;
-                }
-}
-
 }  // namespace bf
 
 extern "C" {
@@ -394,9 +363,12 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
             const double a = kTwoPi * (double)r / (double)bf::kBins;
             tw[c * 16 + b] = make_float2((float)std::cos(a), (float)-std::sin(a));
         }
-    // matrix-core operands of the 128-point up-channelisation (see build_up128_tables)
-    std::vector<_Float16> tw128(bf::kUp128TableHalves);
-    bf::build_up128_tables(tw128.data());
+    // w128^m, m < 128, of the 128-point up-channelisation (FP64 rounded once)
+    std::vector<float2> tw128(128);
+    for (int m = 0; m < 128; ++m) {
+        const double a = kTwoPi * (double)m / 128.0;
+        tw128[m] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    }
 
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { int32_t r = hip_fail(nullptr, e, "hipGetDevice"); delete p; return r; }
@@ -417,7 +389,7 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
         (e = hipMalloc(&p->d_ew, ew_b)) != hipSuccess ||
         (e = hipMalloc(&p->d_tw, tw_b)) != hipSuccess ||
         (e = hipMalloc(&p->d_mf, mf.size())) != hipSuccess ||
-        (e = hipMalloc(&p->d_tw128, tw128.size() * sizeof(_Float16))) != hipSuccess) {
+        (e = hipMalloc(&p->d_tw128, tw128.size() * sizeof(float2))) != hipSuccess) {
         int32_t r = fail(nullptr, BF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
         beamform_destroy(p);
         return r;
@@ -426,7 +398,7 @@ int32_t beamform_init(const bf_config* cfg, const double* chan_freq_hz, int32_t 
         (e = hipMemcpyAsync(p->d_ew, ew.data(), ew_b, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(p->d_tw, tw.data(), tw_b, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(p->d_mf, mf.data(), mf.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(p->d_tw128, tw128.data(), tw128.size() * sizeof(_Float16),
+        (e = hipMemcpyAsync(p->d_tw128, tw128.data(), tw128.size() * sizeof(float2),
                             hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess) {
         int32_t r = hip_fail(nullptr, e, "table upload");
@@ -481,7 +453,7 @@ int32_t beamform_frame_upchan128(bf_plan* p, const uint8_t* d_in, int32_t n_fram
     a.ew = p->d_ew;
     a.tw = p->d_tw;
     a.mf = p->d_mf;
-    a.mf128 = p->d_tw128;
+    a.tw128 = p->d_tw128;
     a.n_chan = p->n_chan;
     a.n_units = n_frames * p->n_chan;
     a.n_blk = p->cfg.n_time / bf::kUp;

@@ -78,9 +78,9 @@ struct LaunchArgs {
     // sub-channel k, line (p, j)) go to fine[unit][it][k][p * 4 + j][m]
     // (complex FP32).
     float2* fine;
-    // 128-point up-channelisation: matrix-core operands of every bin
-    // (build_up128_tables)
-    const void* mf128;
+    // 128-point up-channelisation: tw128[m] = w128^m, m < 128 (FP64 rounded
+    // once)
+    const float2* tw128;
 };
 
 // Rows (channel-frames) of the fixed E-W weight table of the allocation-free
@@ -108,9 +108,5 @@ hipError_t launch_mfma_up128(const LaunchArgs& a, hipStream_t stream);
 //   [64][8] float2      per-lane inter-stage twiddles w512^(b c)
 constexpr size_t kMfmaTableBytes = (8 * 64 + 4 * 64) * 16 + 64 * 8 * 8;
 void build_mfma_tables(void* host_buf);
-// Per-bin matrices of the 128-point up-channelisation, fragment order
-// [16 bins][2 K-steps][hi, lo][64 lanes][8 halves].
-constexpr size_t kUp128TableHalves = 16 * 2 * 2 * 64 * 8;
-void build_up128_tables(_Float16* host_buf);
 
 }  // namespace bf

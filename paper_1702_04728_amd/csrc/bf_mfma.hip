@@ -439,6 +439,10 @@ __global__ __launch_bounds__(kThreads128) __attribute__((amdgpu_waves_per_eu(2, 
 void bf_mfma_up128_kernel(LaunchArgs a)
 {
     __shared__ __align__(16) float4 s_T[8 * kSlice128];  // 8 fine slices, then per-bin powers
+    __shared__ __align__(16) float2 s_w128[128];         // w128^m
+    // the N-S matrix-core tables, read back per bin: held in registers through
+    // the time DFT they would push the kernel into spills
+    __shared__ __align__(16) uint4 s_ns[kMfmaTableBytes / 16];
 
     const Work128 wk = work128_of_block();
     if (wk.unit >= a.n_units) return;  // uniform across the workgroup
@@ -447,8 +451,8 @@ void bf_mfma_up128_kernel(LaunchArgs a)
     const int qw = q128_of_wave(wk.par, w);
     const int row = wk.unit % a.n_chan;
 
-    NsTables mt;
-    load_ns_tables(a.mf, mt, lane);
+    for (int i = t; i < (int)(kMfmaTableBytes / 16); i += kThreads128)
+        s_ns[i] = reinterpret_cast<const uint4*>(a.mf)[i];
     float2 W[4][4];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -466,17 +470,20 @@ void bf_mfma_up128_kernel(LaunchArgs a)
             for (int i = 0; i < 4; ++i) acc[j][nu][i] = 0.f;
 
     const int n_blk128 = a.n_time / 128;
-    const half8* mf128 = reinterpret_cast<const half8*>(a.mf128);
+    if (t < 128) s_w128[t] = a.tw128[t];
+    __syncthreads();
     for (int blk = 0; blk < n_blk128; ++blk) {
         for (int i = 0; i < 8; ++i) {
             const int k = k128_of(wk.par, i);
-            time_dft128_bin(k, src, blk * 128 * kInputs, mf128 + k * 4 * 64,
+            time_dft128_bin(k, src, blk * 128 * kInputs, s_w128,
                             reinterpret_cast<float*>(s_T), t);
             __syncthreads();
             half8 A[4][2];
             [[maybe_unused]] half8 Alo[4][2];
             ew_fragments<kEw, kSplitV>(s_T + r128_for(k, qw) * kSlice128, W, A, Alo, q, n);
             __syncthreads();
+            NsTables mt;
+            load_ns_tables(s_ns, mt, lane);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll

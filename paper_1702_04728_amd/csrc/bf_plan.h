@@ -32,7 +32,7 @@ struct bf_plan {
     } ew_track[2];
     int ew_track_next = 0;
     // 128-point up-channelisation: the w128^(k m) table
-    _Float16* d_tw128 = nullptr;  // matrix-core operands of the 128-point form
+    float2* d_tw128 = nullptr;
     // Allocation-free tracking: this device's fixed weight table (library-wide,
     // not owned by the plan) and the event that tells when its upload has read
     // the host staging table.
