@@ -460,23 +460,65 @@ constexpr int kSlice128 = 1025;
 // Bin k (class S0 = k mod 4) of the 128-point DFT of one 128-sample block for
 // all 2048 inputs: the 8 fine slices r go to T[(r * kSlice128 + slot) * 4 +
 // 2 pol + re/im].  With t = u + 8 t1 + 32 t2 within the block,
-//   y_u[t1]    = sum_t2 x[t] (-i)^(S0 t2)      (exact integers, stride_sum)
+//   y_u[t1]    = sum_t2 x[t] (-i)^(S0 t2)      (exact integers, stride_sums128)
 //   X[k + 16r] = sum_(u, t1) w128^(k (u + 8 t1)) w8^(r u) y_u[t1],
-// the second a real 64 x 16 matrix per bin on the matrix cores (two K-steps of
-// 32, kappa = u div 4; exact FP16 operands, FP32 results).  Each matrix entry
-// is the single power w128^(k (u + 8 t1) + 16 r u) (w8 = w128^16), read from
-// w128[] (FP32, LDS) and split into FP16 hi + lo in the lane that holds it
-// (lane (g, n): K = (u = 4 kappa + g, t1, re/im), column n = slice r = n mod 8
-// of the real (n < 8) or imaginary output part): formed per bin in the
-// kernel, no table of per-bin matrices competes with the sample block for L2.  Wave w takes inputs 256 w .. 256 w + 255 as two
-// sets of 128: lane (g, rr) reads the 8 bytes (inputs) at word column
-// 64 w + 32 m + 2 rr of sample phases u = g and 4 + g (16 lanes: one whole
-// 128-byte line of a row per load), forms their stride sums, and holds row rr
-// of tile e (input 4 (64 w + 32 m + 2 rr) + e) for K-step kappa = u div 4.  A
-// zero-valued input stays exactly zero.
+// the second a real 64 x 16 matrix per bin on the matrix cores (slices128; two
+// K-steps of 32, kappa = u div 4; exact FP16 operands, FP32 results).  Each
+// matrix entry is the single power w128^(k (u + 8 t1) + 16 r u) (w8 = w128^16),
+// read from w128[] (FP32, LDS) and split into FP16 hi + lo in the lane that
+// holds it (lane (g, n): K = (u = 4 kappa + g, t1, re/im), column n = slice
+// r = n mod 8 of the real (n < 8) or imaginary output part): formed per bin in
+// the kernel, so no table of per-bin matrices competes with the sample blocks
+// for L2.  Wave w takes inputs 256 w .. 256 w + 255 as two sets of 128: lane
+// (g, rr) reads the 8 bytes (inputs) at word column 64 w + 32 m + 2 rr of
+// sample phases u = g and 4 + g (16 lanes: one whole 128-byte line of a row per
+// load), forms their stride sums, and holds row rr of tile e (input
+// 4 (64 w + 32 m + 2 rr) + e) for K-step kappa = u div 4.  A zero-valued input
+// stays exactly zero.  Bins k and k + 4 (k and k + 12) share a class, hence
+// their stride sums.
+
+// The stride sums of one 128-sample block for this lane (two sets of 8 inputs,
+// sample phases g and 4 + g, class S0): y[m][kappa] as time_y's words.
+struct Y128 {
+    uint32_t r[2][2][4][2], i[2][2][4][2];  // [set m][kappa][t1][word]
+};
 template <int S0>
-__device__ __forceinline__ void time_dft128(int k, __amdgpu_buffer_rsrc_t src, int blk_off,
-                                            const float2* __restrict__ w128, float* __restrict__ T, int t)
+__device__ __forceinline__ void stride_sums128(__amdgpu_buffer_rsrc_t src, int blk_off, Y128& y, int t)
+{
+    const int lane = t & 63, w = t >> 6, g = lane >> 4, rr = lane & 15;
+    // this lane's sample phase g (+ 4 kappa) row and word columns, in bytes;
+    // the rest of each row offset is uniform (scalar)
+    const int lane_off = g * kInputs + 4 * (64 * w + 2 * rr);
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int kap = 0; kap < 2; ++kap) {
+            // one phase at a time: without the barrier the scheduler hoists
+            // every phase's loads and runs out of registers
+            __builtin_amdgcn_sched_barrier(0);
+            uint2 raw[16];
+#pragma unroll
+            for (int tau = 0; tau < 16; ++tau)
+                raw[tau] = load_pair(src, lane_off + 128 * m, blk_off + (4 * kap + 8 * tau) * kInputs);
+            time_y<S0>(raw, y.r[m][kap], y.i[m][kap]);
+        }
+}
+__device__ __forceinline__ void stride_sums128_class(int s0, __amdgpu_buffer_rsrc_t src, int blk_off,
+                                                     Y128& y, int t)
+{
+    switch (s0) {
+    case 0: stride_sums128<0>(src, blk_off, y, t); break;
+    case 1: stride_sums128<1>(src, blk_off, y, t); break;
+    case 2: stride_sums128<2>(src, blk_off, y, t); break;
+    default: stride_sums128<3>(src, blk_off, y, t); break;
+    }
+}
+
+// The 8 fine slices of bin k from the block's stride sums of class k mod 4
+// (time_dft128): the bin's matrix in this lane's fragments, one tile per input
+// e of each set, stores into T.
+__device__ __forceinline__ void slices128(int k, const Y128& y, const float2* __restrict__ w128,
+                                          float* __restrict__ T, int t)
 {
     const int lane = t & 63, w = t >> 6, g = lane >> 4, rr = lane & 15;
     half8 Bh[2], Bl[2];
@@ -498,36 +540,20 @@ __device__ __forceinline__ void time_dft128(int k, __amdgpu_buffer_rsrc_t src, i
             }
         }
     }
-    const half8 B0h = Bh[0], B0l = Bl[0], B1h = Bh[1], B1l = Bl[1];
     // output column of this lane: slice r = rr mod 8, real (nu = 0) or imaginary
     // part; its stores are this base plus compile-time offsets
     float* const Tl = T + (((rr & 7) * kSlice128 + 128 * w + 16 * g) * 4 + (rr >> 3));
-    // this lane's sample phase g (+ 4 kappa) row and word columns, in bytes;
-    // the rest of each row offset is uniform (scalar)
-    const int lane_off = g * kInputs + 4 * (64 * w + 2 * rr);
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-        // one set at a time: without the barrier the scheduler hoists every
-        // set's loads and runs out of registers
-        __builtin_amdgcn_sched_barrier(0);
-        uint32_t yr[2][4][2], yi[2][4][2];
-#pragma unroll
-        for (int kap = 0; kap < 2; ++kap) {
-            uint2 raw[16];
-#pragma unroll
-            for (int tau = 0; tau < 16; ++tau)
-                raw[tau] = load_pair(src, lane_off + 128 * m, blk_off + (4 * kap + 8 * tau) * kInputs);
-            time_y<S0>(raw, yr[kap], yi[kap]);
-        }
+    for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const half8 A0 = y_fragment(yr[0], yi[0], e >> 2, e & 3);
-            const half8 A1 = y_fragment(yr[1], yi[1], e >> 2, e & 3);
+            const half8 A0 = y_fragment(y.r[m][0], y.i[m][0], e >> 2, e & 3);
+            const half8 A1 = y_fragment(y.r[m][1], y.i[m][1], e >> 2, e & 3);
             const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
-            floatx4 X = mfma16(A0, B0h, zero);
-            X = mfma16(A0, B0l, X);
-            X = mfma16(A1, B1h, X);
-            X = mfma16(A1, B1l, X);
+            floatx4 X = mfma16(A0, Bh[0], zero);
+            X = mfma16(A0, Bl[0], X);
+            X = mfma16(A1, Bh[1], X);
+            X = mfma16(A1, Bl[1], X);
             // row 4 g + i: input 4 (64 w + 32 m + 8 g + 2 i + (e >> 2)) + (e & 3),
             // i.e. slot 2 (64 w + 32 m + 8 g + 2 i + (e >> 2)) + ((e & 3) >> 1),
             // pol e & 1
@@ -535,18 +561,16 @@ __device__ __forceinline__ void time_dft128(int k, __amdgpu_buffer_rsrc_t src, i
             for (int i = 0; i < 4; ++i)
                 Tl[(64 * m + 4 * i + 2 * (e >> 2) + ((e & 3) >> 1)) * 4 + 2 * (e & 1)] = X[i];
         }
-    }
 }
 
+// One bin, stride sums and slices together (the FP32 kernel, which has no
+// registers to keep the sums across bins).
 __device__ __forceinline__ void time_dft128_bin(int k, __amdgpu_buffer_rsrc_t src, int blk_off,
                                                 const float2* w128, float* T, int t)
 {
-    switch (k & 3) {
-    case 0: time_dft128<0>(k, src, blk_off, w128, T, t); break;
-    case 1: time_dft128<1>(k, src, blk_off, w128, T, t); break;
-    case 2: time_dft128<2>(k, src, blk_off, w128, T, t); break;
-    default: time_dft128<3>(k, src, blk_off, w128, T, t); break;
-    }
+    Y128 y;
+    stride_sums128_class(k & 3, src, blk_off, y, t);
+    slices128(k, y, w128, T, t);
 }
 
 // End of frame, 128-point form: P[(w * 4 + j) * 512 + bin] holds wave w's

@@ -473,10 +473,14 @@ void bf_mfma_up128_kernel(LaunchArgs a)
     if (t < 128) s_w128[t] = a.tw128[t];
     __syncthreads();
     for (int blk = 0; blk < n_blk128; ++blk) {
-        for (int i = 0; i < 8; ++i) {
+        // bins in pairs of one class (i and i + 4: k and k + 4, or k and
+        // k + 12), which share the block's stride sums
+        Y128 y;
+        for (int i0 = 0; i0 < 8; ++i0) {
+            const int i = (i0 >> 1) + 4 * (i0 & 1);
             const int k = k128_of(wk.par, i);
-            time_dft128_bin(k, src, blk * 128 * kInputs, s_w128,
-                            reinterpret_cast<float*>(s_T), t);
+            if ((i0 & 1) == 0) stride_sums128_class(k & 3, src, blk * 128 * kInputs, y, t);
+            slices128(k, y, s_w128, reinterpret_cast<float*>(s_T), t);
             __syncthreads();
             half8 A[4][2];
             [[maybe_unused]] half8 Alo[4][2];
