@@ -393,9 +393,10 @@ def main():
                     help="frames at the start of each sweep point left out of its statistics")
     ap.add_argument("--sweep-chunk", type=int, default=0,
                     help="samples per serving-loop launch in the sweep (0: whole frames)")
-    ap.add_argument("--sweep-list", default="512,576,640,704,768",
-                    help="channel counts of the paced sweep, ascending (the full sweep: "
-                         "64,128,192,256,320,384,448,512,544,576,608,640,704,768)")
+    ap.add_argument("--sweep-list", default="512,576,640,704,768,832,896",
+                    help="channel counts of the paced sweep, ascending; it continues past the "
+                         "nominal 512 until real time fails (the full sweep: 64,128,192,256,"
+                         "320,384,448,512,544,576,608,640,672,704,736,768,832,896)")
     ap.add_argument("--warmup-seconds", type=float, default=2.0,
                     help="seconds of untimed launches of the first path before any timing")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
