@@ -8,7 +8,10 @@ resident in HBM before timing), producing 1024 beams x 16 sub-channels per
 channel-frame.  Value = channel-frames per second x 0.98304 ms, the batch
 throughput expressed in real-time channels.  The paced figure -- channels whose
 0.983 ms frames the serving loop completes with p99 latency inside the frame
-time (config-4 inputs) -- is under "sustained", per path.
+time (config-4 inputs; device-gated pacing: launches queued ahead of their data
+and held on the device until each chunk arrives, so that a stall of the HIP
+runtime's launch calls delays no frame; host-paced with --pacing host) -- is
+under "sustained", per path, with the host-paced loop's figures at that point.
 
 Prints ONE JSON line (rank 0).  The library runs on one GPU (channels would
 shard across GPUs with no exchange): --gpus above 1 exits with a message.
@@ -249,7 +252,7 @@ def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None, u8=None, u
     }
 
 
-def serve(torch, bf, synth, prec, n_frames: int, to_clamps: bool = False):
+def serve(torch, bf, synth, prec, n_frames: int, to_clamps: bool = False, pacing="gated"):
     """Serving loop (config 3): seeded churn of 16-128 channels from 1024 ids, 0.983 ms
     frames paced in real time, hipGraph replay; input ring of 8 frames x 128 slots
     (805 MB, larger than the 256 MB Infinity Cache) tiled from 16 seeded frames.
@@ -271,7 +274,7 @@ def serve(torch, bf, synth, prec, n_frames: int, to_clamps: bool = False):
     del pool
     lat = np.zeros(n_frames)
     with bf.Beamformer([600e6], precision=prec) as b:
-        st, slot_log = b.stream(ring, out, events, n_frames, pacing=True, use_graph=True,
+        st, slot_log = b.stream(ring, out, events, n_frames, pacing=pacing, use_graph=True,
                                 log_slots=True, latency_log=lat)
     torch.cuda.synchronize()
     del ring, out
@@ -285,7 +288,7 @@ def serve(torch, bf, synth, prec, n_frames: int, to_clamps: bool = False):
         by_active[str(k)] = {"frames": int(sel.size),
                              "latency_p50_ms": round(float(np.percentile(sel, 50)), 4),
                              "latency_p99_ms": round(float(np.percentile(sel, 99)), 4)}
-    return {"frames": st["frames"], "budget_ms": 0.98304,
+    return {"frames": st["frames"], "budget_ms": 0.98304, "pacing": pacing,
             "latency_by_active_channels": by_active,
             "latency_p50_ms": round(st["latency_p50_ms"], 4),
             "latency_p99_ms": round(st["latency_p99_ms"], 4),
@@ -299,15 +302,44 @@ def serve(torch, bf, synth, prec, n_frames: int, to_clamps: bool = False):
             "channel_frames": st["channel_frames"], "wall_s": round(st["wall_s"], 3)}
 
 
+def sweep_point(torch, bf, synth, pool, prec, n, n_frames, chunk, warmup, pacing):
+    """One sweep point: N config-4 channels, all active, paced; the point's figures."""
+    depth = 4
+    idx = torch.tensor([(7 * k + s) % 16 for k in range(depth) for s in range(n)],
+                       device="cuda")
+    ring = pool[idx].reshape(depth, n, 384, 2048).contiguous()
+    out = torch.empty((depth, n, 1024, 16), dtype=torch.float32, device="cuda")
+    c_idx = synth.sweep_c_idx(n)
+    events = [(0, 1, int(c), float(synth.chan_freq_hz(c))) for c in c_idx]
+    with bf.Beamformer([600e6], precision=prec) as b:
+        st, _ = b.stream(ring, out, events, n_frames, chunk=chunk, pacing=pacing,
+                         use_graph=True, log_slots=False, warmup_frames=warmup)
+    torch.cuda.synchronize()
+    del ring, out
+    ok = st["latency_p99_ms"] <= 0.98304 and st["frames"] == n_frames
+    row = {"channels": n, "sustained": ok,
+           "latency_p50_ms": round(st["latency_p50_ms"], 4),
+           "latency_p99_ms": round(st["latency_p99_ms"], 4),
+           "service_mean_ms": round(st["service_mean_ms"], 4),
+           "service_p99_ms": round(st["service_p99_ms"], 4),
+           "late_frames": st["late_frames"],
+           "input_GBs": round(st["input_gb_s"], 1)}
+    log("%s sweep %s chunk %d N=%d: p99 %.3f ms service %.3f ms late %d -> %s" % (
+        prec, pacing, chunk or 384, n, st["latency_p99_ms"], st["service_mean_ms"],
+        st["late_frames"], "sustained" if ok else "not sustained"))
+    return row
+
+
 def sweep(torch, bf, synth, prec, n_list, n_frames: int, chunk: int = 0, warmup: int = 200,
-          descend: bool = True):
+          descend: bool = True, pacing="gated"):
     """Config 4: N channels spread over 400-800 MHz (c_idx = floor((i + 1/2) 1024 / N)),
     all active, frames paced in real time through the serving loop, ingested in chunks
     of `chunk` samples (0: whole frames); N is sustained when the p99 frame latency of
     the frames after the first `warmup` stays within the 0.983 ms budget.  Input ring:
     4 frames per slot tiled from 16 seeded config-4 frames (noise, DM-500 pulse, RFI
     tones).  The points run in ascending order until one fails; if the first fails,
-    N steps down by 64 until one holds (descend)."""
+    N steps down by 64 until one holds (descend).  With device-gated pacing the
+    host-paced loop is also run at the largest sustained point, for comparison."""
     pool_c = synth.sweep_c_idx(16)
     pool_np = synth.config4_frames(1004, pool_c, [0]).reshape(16, 384, 2048)
     pool = torch.from_numpy(pool_np).cuda()
@@ -318,37 +350,21 @@ def sweep(torch, bf, synth, prec, n_list, n_frames: int, chunk: int = 0, warmup:
     while k < len(n_list):
         n = n_list[k]
         k += 1
-        depth = 4
-        idx = torch.tensor([(7 * k + s) % 16 for k in range(depth) for s in range(n)],
-                           device="cuda")
-        ring = pool[idx].reshape(depth, n, 384, 2048).contiguous()
-        out = torch.empty((depth, n, 1024, 16), dtype=torch.float32, device="cuda")
-        c_idx = synth.sweep_c_idx(n)
-        events = [(0, 1, int(c), float(synth.chan_freq_hz(c))) for c in c_idx]
-        with bf.Beamformer([600e6], precision=prec) as b:
-            st, _ = b.stream(ring, out, events, n_frames, chunk=chunk, pacing=True,
-                             use_graph=True, log_slots=False, warmup_frames=warmup)
-        torch.cuda.synchronize()
-        del ring, out
-        ok = st["latency_p99_ms"] <= 0.98304 and st["frames"] == n_frames
-        rows.append({"channels": n, "sustained": ok,
-                     "latency_p50_ms": round(st["latency_p50_ms"], 4),
-                     "latency_p99_ms": round(st["latency_p99_ms"], 4),
-                     "service_mean_ms": round(st["service_mean_ms"], 4),
-                     "service_p99_ms": round(st["service_p99_ms"], 4),
-                     "late_frames": st["late_frames"],
-                     "input_GBs": round(st["input_gb_s"], 1)})
-        log("%s sweep chunk %d N=%d: p99 %.3f ms service %.3f ms late %d -> %s" % (
-            prec, chunk or 384, n, st["latency_p99_ms"], st["service_mean_ms"], st["late_frames"],
-            "sustained" if ok else "not sustained"))
+        row = sweep_point(torch, bf, synth, pool, prec, n, n_frames, chunk, warmup, pacing)
+        rows.append(row)
+        ok = row["sustained"]
         if ok:
             best = max(best, n)
         elif best == 0 and n - 64 >= 64 and descend:
             n_list.insert(k, n - 64)  # the first point failed: step down until one holds
         else:
             break
+    host = None
+    if pacing == "gated" and best > 0:
+        host = sweep_point(torch, bf, synth, pool, prec, best, n_frames, chunk, warmup, "host")
     return {"max_channels_sustained": best, "frames_per_point": n_frames,
-            "warmup_frames": warmup, "chunk_samples": chunk or 384, "points": rows}
+            "warmup_frames": warmup, "chunk_samples": chunk or 384, "pacing": pacing,
+            "points": rows, "host_paced_at_sustained": host}
 
 
 def sustained_summary(sw):
@@ -364,7 +380,9 @@ def sustained_summary(sw):
             "criterion": "p99 frame latency <= 0.98304 ms over %d paced frames after %d "
                          "warm-up frames" % (sw["frames_per_point"] - sw["warmup_frames"],
                                              sw["warmup_frames"]),
-            "points_tried": [r["channels"] for r in sw["points"]]}
+            "pacing": sw.get("pacing"),
+            "points_tried": [r["channels"] for r in sw["points"]],
+            "host_paced_same_channels": sw.get("host_paced_at_sustained")}
 
 
 def main():
@@ -397,6 +415,10 @@ def main():
                     help="channel counts of the paced sweep, ascending; it continues past the "
                          "nominal 512 until real time fails (the full sweep: 64,128,192,256,"
                          "320,384,448,512,544,576,608,640,672,704,736,768,832,896)")
+    ap.add_argument("--pacing", default="gated", choices=["gated", "host"],
+                    help="real-time pacing of the serving loop and the sweep: device-gated "
+                         "(launches queued ahead, held on the device until their data "
+                         "arrive) or host-paced (each launch issued at its data's arrival)")
     ap.add_argument("--warmup-seconds", type=float, default=2.0,
                     help="seconds of untimed launches of the first path before any timing")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -479,15 +501,17 @@ def main():
 
     if args.serve_frames > 0:
         for prec in paths:
-            results[prec]["serving"] = serve(torch, bf, synth, prec, args.serve_frames)
+            results[prec]["serving"] = serve(torch, bf, synth, prec, args.serve_frames,
+                                             pacing=args.pacing)
             results[prec]["serving_to_clamps"] = serve(torch, bf, synth, prec, args.serve_frames,
-                                                       to_clamps=True)
+                                                       to_clamps=True, pacing=args.pacing)
 
     if not args.no_sweep:
         n_list = [int(v) for v in args.sweep_list.split(",")]
         for prec in paths:
             results[prec]["sweep"] = sweep(torch, bf, synth, prec, n_list, args.sweep_frames,
-                                           args.sweep_chunk, args.sweep_warmup)
+                                           args.sweep_chunk, args.sweep_warmup,
+                                           pacing=args.pacing)
 
     head = results[paths[0]]
     res = {

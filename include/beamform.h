@@ -217,6 +217,10 @@ int32_t beamform_frame_tracking_noalloc(bf_plan *plan, const uint8_t *d_in, int3
 #define BF_STREAM_JOIN 1
 #define BF_STREAM_LEAVE 2
 #define BF_STREAM_MAX_SLOTS 1024
+#define BF_STREAM_PACE_NONE 0
+#define BF_STREAM_PACE_HOST 1
+#define BF_STREAM_PACE_GATED 2
+#define BF_STREAM_RUN_AHEAD 16 /* launches queued and not yet completed, at most */
 
 typedef struct {
     int32_t frame;       /* applied before frame `frame` is processed */
@@ -236,9 +240,17 @@ typedef struct {
     int32_t n_frames;         /* frames to run (>= 0) */
     int32_t chunk;            /* samples per launch: a multiple of 16 dividing n_time
                                  (0 = n_time, whole frames) */
-    int32_t pacing;           /* 0: launch as fast as possible; 1: real time, chunk c of
-                                 frame i becomes available at t0 + (i n_time + (c+1) chunk)
-                                 x 2.56 us */
+    int32_t pacing;           /* BF_STREAM_PACE_*: 0 launch as fast as possible; 1 real
+                                 time, host-paced: chunk c of frame i becomes available at
+                                 t0 + (i n_time + (c+1) chunk) x 2.56 us and the host
+                                 launches it then; 2 real time, device-gated: the same
+                                 availability times, published by a receiver thread as an
+                                 arrival count in pinned host memory; the host queues
+                                 launches ahead of their data (up to BF_STREAM_RUN_AHEAD
+                                 launches not yet completed) and a one-wave kernel in
+                                 front of each holds the stream until its chunk's arrival
+                                 is published, so a host or HIP-runtime stall shorter than
+                                 the queued work delays no frame */
     int32_t use_graph;        /* 1: replay one captured hipGraph per launch; 0: plain launches */
     int64_t mem_cap_bytes;    /* device bytes the stream may use for channel state and its
                                  share of the rings (0: free memory at start); a JOIN that
@@ -254,7 +266,8 @@ typedef struct {
     const uint8_t *ingest_ok; /* optional host u8 [n_frames][max_slots], set by the ingest
                                  (the paper's data arrive over lossy links): nonzero when
                                  frame i of slot s arrived complete by its availability
-                                 time; read when the frame's first chunk is launched.  A
+                                 time; read when the frame's first chunk is launched
+                                 (queued, with device-gated pacing).  A
                                  zero (empty or late ring entry) skips that channel-frame:
                                  its output entry is written as zeros, flagged invalid in
                                  d_out_valid and counted in missing_frames.  NULL: every
@@ -264,6 +277,19 @@ typedef struct {
                                  0 = zeros for a missing frame */
     double *latency_log_ms;   /* optional host [n_frames]: each frame's latency in ms
                                  (warm-up frames included), filled before returning */
+    double *service_log_ms;   /* optional host [n_frames]: device time of each frame's
+                                 launches in ms (event to event), filled before returning */
+    double *issue_log_ms;     /* optional host [n_frames]: host time at which each frame's
+                                 last launch had been issued, minus the availability of
+                                 its last chunk, in ms (with pacing: how late the host
+                                 issued it; a latency well above the service time with a
+                                 small issue lag means the frame queued behind earlier
+                                 ones on the device; negative: queued ahead of its data,
+                                 device-gated pacing), filled before returning */
+    int32_t gate_timeout_ms;  /* device-gated pacing: longest wait of one launch for its
+                                 chunk's arrival before the loop fails with BF_E_DEVICE
+                                 (a receiver that stopped); 0 = 1000 ms */
+    int32_t reserved2;        /* must be 0 */
 } bf_stream_desc;
 
 typedef struct {
@@ -289,14 +315,16 @@ typedef struct {
 
 /* Run the serving loop on the plan's geometry and precision (the plan's own
  * channel list is not used; channels come from JOIN events).  Frame i:
- * apply its events; (paced) wait for each chunk's availability; launch the
- * beamformer for every active slot; the last chunk writes the frame's output.
- * Latency of frame i = time its last launch completes - availability of its
- * last chunk (host steady clock).  Blocks until all frames completed; `stream`
- * is synchronised with before the first launch and after the last.  Library
- * state (slot tables, partial accumulators, graph) is allocated at start and
- * freed before returning.  Errors: BF_E_INVAL for a bad descriptor,
- * BF_E_DEVICE for HIP failures. */
+ * apply its events; (host-paced) wait for each chunk's availability, or
+ * (device-gated) queue a wait for it on the device; launch the beamformer for
+ * every active slot; the last chunk writes the frame's output.  Latency of
+ * frame i = time its last launch completes - availability of its last chunk
+ * (host steady clock).  Blocks until all frames completed; `stream` is
+ * synchronised with before the first launch and after the last.  Library
+ * state (slot tables, partial accumulators, graph, the receiver's pinned
+ * words and thread) is allocated at start and freed before returning.
+ * Errors: BF_E_INVAL for a bad descriptor, BF_E_DEVICE for HIP failures and
+ * for a device-gated wait that exceeded gate_timeout_ms. */
 int32_t beamform_stream(bf_plan *plan, const bf_stream_desc *desc, bf_stream_stats *stats,
                         void *stream);
 

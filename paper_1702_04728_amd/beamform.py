@@ -22,6 +22,7 @@ _PRECISION = {"fp32": FP32_FFT, "fp16": FP16_MFMA, "fp32_mfma": FP32_MFMA,
               FP32_FFT: FP32_FFT, FP16_MFMA: FP16_MFMA, FP32_MFMA: FP32_MFMA}
 
 N_INPUTS = 2048
+PACING = {"none": 0, "host": 1, "gated": 2}  # bf_stream_desc.pacing
 N_BEAMS = 1024
 N_UPCHAN = 16
 N_BEAM_NS = 256
@@ -77,7 +78,10 @@ class BfStreamDesc(ctypes.Structure):
                 ("slot_log", ctypes.POINTER(ctypes.c_int32)),
                 ("ingest_ok", ctypes.POINTER(ctypes.c_uint8)),
                 ("d_out_valid", ctypes.c_void_p),
-                ("latency_log_ms", ctypes.POINTER(ctypes.c_double))]
+                ("latency_log_ms", ctypes.POINTER(ctypes.c_double)),
+                ("service_log_ms", ctypes.POINTER(ctypes.c_double)),
+                ("issue_log_ms", ctypes.POINTER(ctypes.c_double)),
+                ("gate_timeout_ms", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class BfStreamStats(ctypes.Structure):
@@ -107,6 +111,15 @@ def _events_array(events):
     return arr, len(ev)
 
 
+def _pacing(p):
+    """pacing as False/True (none/host-paced), "none"/"host"/"gated", or the C value."""
+    if isinstance(p, str):
+        if p not in PACING:
+            raise ValueError("pacing must be one of %s" % sorted(PACING))
+        return PACING[p]
+    return int(p)
+
+
 def _stream_desc(depth, max_slots, n_frames, chunk, pacing, use_graph, mem_cap_bytes, events,
                  slot_log, d_in=None, d_out=None, warmup_frames=0, ingest_ok=None,
                  d_out_valid=None):
@@ -115,7 +128,7 @@ def _stream_desc(depth, max_slots, n_frames, chunk, pacing, use_graph, mem_cap_b
     d.d_in_ring = d_in
     d.d_out_ring = d_out
     d.depth, d.max_slots, d.n_frames, d.chunk = int(depth), int(max_slots), int(n_frames), int(chunk)
-    d.pacing, d.use_graph, d.mem_cap_bytes = int(pacing), int(use_graph), int(mem_cap_bytes)
+    d.pacing, d.use_graph, d.mem_cap_bytes = _pacing(pacing), int(use_graph), int(mem_cap_bytes)
     d.events = arr
     d.n_events = n_ev
     d.warmup_frames = int(warmup_frames)
@@ -134,12 +147,15 @@ def _stream_desc(depth, max_slots, n_frames, chunk, pacing, use_graph, mem_cap_b
 
 
 def stream_schedule(events, n_frames, max_slots, per_slot_bytes, cap_bytes, depth=1,
-                    warmup_frames=0, ingest_ok=None):
-    """Host-only dry run of the serving loop's scheduler: (stats dict, slot_log)."""
+                    warmup_frames=0, ingest_ok=None, pacing=0, gate_timeout_ms=0):
+    """Host-only dry run of the serving loop's scheduler: (stats dict, slot_log).  The
+    descriptor (pacing and gate_timeout_ms included) is validated as beamform_stream
+    validates it."""
     lib = load_library()
     log = np.full((n_frames, max_slots), -1, dtype=np.int32)
-    d, keep = _stream_desc(depth, max_slots, n_frames, 0, 0, 0, 0, events, log,
+    d, keep = _stream_desc(depth, max_slots, n_frames, 0, pacing, 0, 0, events, log,
                            warmup_frames=warmup_frames, ingest_ok=ingest_ok)
+    d.gate_timeout_ms = int(gate_timeout_ms)
     st = BfStreamStats()
     _check(lib.beamform_stream_schedule(ctypes.byref(d), int(per_slot_bytes), int(cap_bytes),
                                         ctypes.byref(st)))
@@ -391,15 +407,20 @@ class Beamformer:
 
     def stream(self, in_ring, out_ring, events, n_frames, chunk=0, pacing=False, use_graph=True,
                mem_cap_bytes=0, stream=None, log_slots=True, warmup_frames=0, ingest_ok=None,
-               out_valid=None, latency_log=None):
+               out_valid=None, latency_log=None, service_log=None, issue_log=None,
+               gate_timeout_ms=0):
         """Run the serving loop (blocking).  in_ring: CUDA uint8 [depth][max_slots][n_time][2048];
         out_ring: CUDA float32 [depth][max_slots][1024][16]; events: (frame, op, channel_id,
-        freq_hz) tuples sorted by frame; latency and service statistics leave out the first
+        freq_hz) tuples sorted by frame; pacing: False / "none" (as fast as possible),
+        True / "host" (host-paced real time) or "gated" (device-gated real time: launches
+        queued ahead of their data, gate_timeout_ms bounding one wait, 0 = 1 s);
+        latency and service statistics leave out the first
         warmup_frames frames.  ingest_ok: host uint8 [n_frames][max_slots], 0 where a
         channel-frame did not arrive (its output is zeroed and flagged); out_valid: CUDA
         uint8 [depth][max_slots] receiving those flags; latency_log: host float64
-        [n_frames] receiving each frame's latency in ms.  Returns (stats dict, slot_log
-        [n_frames][max_slots])."""
+        [n_frames] receiving each frame's latency in ms; service_log, issue_log: the same
+        for each frame's device time and for how late its last launch was issued after
+        its availability.  Returns (stats dict, slot_log [n_frames][max_slots])."""
         import torch
         if not (isinstance(in_ring, torch.Tensor) and in_ring.is_cuda and in_ring.dtype == torch.uint8
                 and in_ring.is_contiguous() and in_ring.dim() == 4
@@ -424,11 +445,15 @@ class Beamformer:
                                ctypes.c_void_p(out_ring.data_ptr()), warmup_frames, ingest_ok,
                                ctypes.c_void_p(out_valid.data_ptr()) if out_valid is not None
                                else None)
-        if latency_log is not None:
-            if not (isinstance(latency_log, np.ndarray) and latency_log.dtype == np.float64
-                    and latency_log.flags.c_contiguous and latency_log.shape == (n_frames,)):
-                raise ValueError("latency_log must be a contiguous float64 array [%d]" % n_frames)
-            d.latency_log_ms = latency_log.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        for name, arr in (("latency_log", latency_log), ("service_log", service_log),
+                          ("issue_log", issue_log)):
+            if arr is None:
+                continue
+            if not (isinstance(arr, np.ndarray) and arr.dtype == np.float64
+                    and arr.flags.c_contiguous and arr.shape == (n_frames,)):
+                raise ValueError("%s must be a contiguous float64 array [%d]" % (name, n_frames))
+            setattr(d, name + "_ms", arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        d.gate_timeout_ms = int(gate_timeout_ms)
         st = BfStreamStats()
         rc = self.lib.beamform_stream(self._plan, ctypes.byref(d), ctypes.byref(st),
                                       _stream_handle(stream))

@@ -8,8 +8,14 @@
 // slots) host -> device, replay the captured kernel graph, record an event.
 // A completion thread waits on those events in order and timestamps them;
 // frame latency = completion of the frame's last launch - availability of its
-// last chunk.  All device state is allocated when the loop starts and freed
-// before it returns.
+// last chunk.  Host-paced, the host waits for each chunk's availability before
+// launching it.  Device-gated, a receiver thread publishes the arrival count at
+// the availability times, the host queues launches ahead, and a one-wave gate
+// kernel in front of each launch holds the stream until its chunk has arrived:
+// the HIP runtime's launch calls occasionally block for milliseconds, which a
+// host-paced loop passes on to every frame behind the stall and a queue of
+// gated launches absorbs.  All device state is allocated when the loop starts
+// and freed before it returns.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +27,7 @@
 #include <thread>
 #include <vector>
 
+#include "bf_gate.h"
 #include "bf_plan.h"
 #include "bf_trace.h"
 
@@ -28,7 +35,8 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 constexpr double kSampleS = 2.56e-6;
-constexpr int kInFlight = 8;  // launches the host may run ahead of the device
+constexpr int kInFlight = BF_STREAM_RUN_AHEAD;  // launches the host may run ahead of the device
+constexpr int32_t kGateTimeoutMs = 1000;        // default bound of one gated wait
 constexpr size_t kTabBytes = bf::kBeamNS * sizeof(int32_t) + bf::kBeamEW * bf::kCyl * sizeof(float2);
 
 // Channel slots, admission and event application (pure host; no device).
@@ -118,7 +126,15 @@ int32_t check_desc(const bf_stream_desc* d, std::string* msg)
         *msg = "warmup_frames must be in [0, n_frames]";
         return BF_E_INVAL;
     }
-    if (d->pacing != 0 && d->pacing != 1) { *msg = "pacing must be 0 or 1"; return BF_E_INVAL; }
+    if (d->pacing != BF_STREAM_PACE_NONE && d->pacing != BF_STREAM_PACE_HOST &&
+        d->pacing != BF_STREAM_PACE_GATED) {
+        *msg = "pacing must be 0, 1 or 2";
+        return BF_E_INVAL;
+    }
+    if (d->gate_timeout_ms < 0 || d->reserved2 != 0) {
+        *msg = "gate_timeout_ms must be >= 0 and reserved2 0";
+        return BF_E_INVAL;
+    }
     if (d->mem_cap_bytes < 0) { *msg = "mem_cap_bytes < 0"; return BF_E_INVAL; }
     for (int32_t i = 1; i < d->n_events; ++i)
         if (d->events[i].frame < d->events[i - 1].frame) {
@@ -282,11 +298,16 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     bf::StreamState* d_state = nullptr;
     bf::StreamState* h_state = nullptr;
     unsigned char* h_tab = nullptr;
+    const bool gated = d->pacing == BF_STREAM_PACE_GATED;
+    uint32_t* h_gate = nullptr;        // receiver's words (bf_gate.h), coherent pinned memory
+    uint32_t* d_gate = nullptr;        // their device address
+    int32_t* d_gate_err = nullptr;     // set by a gate that timed out
     hipStream_t s = nullptr;
     hipEvent_t ev_start[kInFlight] = {}, ev_end[kInFlight] = {}, ev_sync = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     auto cleanup = [&]() {
+        if (h_gate) __atomic_store_n(&h_gate[1], 1u, __ATOMIC_RELEASE);  // release queued gates
         if (s) (void)hipStreamSynchronize(s);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -302,6 +323,8 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
         if (d_state) (void)hipFree(d_state);
         if (h_state) (void)hipHostFree(h_state);
         if (h_tab) (void)hipHostFree(h_tab);
+        if (h_gate) (void)hipHostFree(h_gate);
+        if (d_gate_err) (void)hipFree(d_gate_err);
     };
     auto fail = [&](const char* what) -> int32_t {
         p->err = std::string(what) + ": " + hipGetErrorString(e);
@@ -318,6 +341,24 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     if ((e = hipHostMalloc((void**)&h_state, sizeof(bf::StreamState) * kInFlight, 0)) != hipSuccess ||
         (e = hipHostMalloc((void**)&h_tab, kTabBytes * S, 0)) != hipSuccess)
         return fail("hipHostMalloc");
+    uint64_t gate_ticks = 0;
+    if (gated) {
+        int khz = 0;
+        if ((e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev)) != hipSuccess)
+            return fail("wall clock rate");
+        if (khz <= 0 || khz > 10000000) {  // a rate in kHz, 10 GHz at most
+            e = hipErrorInvalidValue;
+            return fail("wall clock rate");
+        }
+        gate_ticks = (uint64_t)khz * (uint64_t)(d->gate_timeout_ms ? d->gate_timeout_ms : kGateTimeoutMs);
+        if ((e = hipHostMalloc((void**)&h_gate, sizeof(uint32_t) * bf::kGateWords, hipHostMallocCoherent)) !=
+                hipSuccess ||
+            (e = hipHostGetDevicePointer((void**)&d_gate, h_gate, 0)) != hipSuccess ||
+            (e = hipMalloc(&d_gate_err, sizeof(int32_t))) != hipSuccess)
+            return fail("gate state");
+        __atomic_store_n(&h_gate[0], 0u, __ATOMIC_RELEASE);
+        __atomic_store_n(&h_gate[1], 0u, __ATOMIC_RELEASE);
+    }
     if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return fail("stream");
     for (int k = 0; k < kInFlight; ++k)
         if ((e = hipEventCreate(&ev_start[k])) != hipSuccess ||
@@ -360,11 +401,13 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
             return fail("hipGraphInstantiate");
     }
     // Warm start: one launch with no active slot (every workgroup returns at
-    // once) before the clock starts, so that the first paced frame does not
-    // pay the first replay's one-time setup.
+    // once), and one gate that passes at once, before the clock starts, so that
+    // the first paced frame does not pay the first replay's one-time setup.
     {
         std::memset(&h_state[0], 0, bf::kStreamStateHeader);
-        if ((e = hipMemcpyAsync(d_state, &h_state[0], bf::kStreamStateHeader, hipMemcpyHostToDevice,
+        if ((gated && ((e = hipMemsetAsync(d_gate_err, 0, sizeof(int32_t), s)) != hipSuccess ||
+                       (e = bf::launch_ingest_gate(d_gate, 0u, gate_ticks, d_gate_err, s)) != hipSuccess)) ||
+            (e = hipMemcpyAsync(d_state, &h_state[0], bf::kStreamStateHeader, hipMemcpyHostToDevice,
                                 s)) != hipSuccess ||
             (e = (d->use_graph ? hipGraphLaunch(exec, s) : launch(s))) != hipSuccess ||
             (e = hipStreamSynchronize(s)) != hipSuccess)
@@ -373,7 +416,8 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
 
     // ---- completion thread ----
     std::vector<LaunchRec> recs(kInFlight);
-    std::vector<double> lat_ms((size_t)d->n_frames, 0.0), svc_ms((size_t)d->n_frames, 0.0);
+    std::vector<double> lat_ms((size_t)d->n_frames, 0.0), svc_ms((size_t)d->n_frames, 0.0),
+        issue_ms((size_t)d->n_frames, 0.0);
     std::atomic<int64_t> launched{0}, completed{0};
     std::atomic<bool> stop{false};
     std::atomic<int> thread_err{0};
@@ -414,6 +458,35 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     st->min_active = d->n_frames > 0 ? S : 0;
     const Clock::time_point t_start = Clock::now();
     const Clock::time_point t0 = t_start + std::chrono::microseconds(500);
+    // availability of chunk c of frame i (the last sample's arrival)
+    auto avail_at = [&](int64_t i, int c) {
+        return t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(
+                        ((double)i * n_time + (double)(c + 1) * chunk) * kSampleS));
+    };
+    // wait on the host clock until `when` (sleeping while far, yielding near)
+    // or until `quit` is set
+    auto wait_until = [](Clock::time_point when, const std::atomic<bool>* quit) {
+        for (;;) {
+            const auto now = Clock::now();
+            if (now >= when || (quit && quit->load(std::memory_order_acquire))) return;
+            if (when - now > std::chrono::microseconds(300))
+                std::this_thread::sleep_for(std::chrono::microseconds(100));
+            else
+                std::this_thread::yield();
+        }
+    };
+    // ---- receiver (device-gated pacing): publishes each chunk's arrival ----
+    std::atomic<bool> recv_stop{false};
+    std::thread receiver;
+    if (gated)
+        receiver = std::thread([&]() {
+            const int64_t total = (int64_t)d->n_frames * n_chunks;
+            for (int64_t q = 0; q < total; ++q) {
+                wait_until(avail_at(q / n_chunks, (int)(q % n_chunks)), &recv_stop);
+                if (recv_stop.load(std::memory_order_acquire)) return;
+                __atomic_store_n(&h_gate[0], (uint32_t)(q + 1), __ATOMIC_RELEASE);
+            }
+        });
     int32_t status = BF_OK;
     for (int32_t i = 0; i < d->n_frames && status == BF_OK; ++i) {
         while (evi < d->n_events && d->events[evi].frame <= i) {
@@ -456,22 +529,11 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
         st->max_active = std::max(st->max_active, n_act);
         st->min_active = std::min(st->min_active, n_act);
         for (int c = 0; c < n_chunks; ++c, ++L) {
-            Clock::time_point avail =
-                t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(
-                         ((double)i * n_time + (double)(c + 1) * chunk) * kSampleS));
-            if (d->pacing) {
-                for (;;) {
-                    const auto now = Clock::now();
-                    if (now >= avail) break;
-                    if (avail - now > std::chrono::microseconds(300))
-                        std::this_thread::sleep_for(std::chrono::microseconds(100));
-                    else
-                        std::this_thread::yield();
-                }
-            }
+            Clock::time_point avail = avail_at(i, c);
+            if (d->pacing == BF_STREAM_PACE_HOST) wait_until(avail, nullptr);
             wait_completed(L - kInFlight + 1);  // slot k of the state/event rings is free
             if (thread_err.load()) { status = BF_E_DEVICE; break; }
-            if (!d->pacing) avail = Clock::now();
+            if (d->pacing == BF_STREAM_PACE_NONE) avail = Clock::now();
             const int k = (int)(L % kInFlight);
             bf::StreamState& hs = h_state[k];
             hs.ring_index = i % d->depth;
@@ -482,6 +544,8 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
             recs[k] = LaunchRec{i, c == n_chunks - 1, avail};
             if ((e = hipMemcpyAsync(d_state, &hs, bf::kStreamStateHeader + sizeof(int32_t) * n_act,
                                     hipMemcpyHostToDevice, s)) != hipSuccess ||
+                (gated && (e = bf::launch_ingest_gate(d_gate, (uint32_t)(L + 1), gate_ticks, d_gate_err,
+                                                      s)) != hipSuccess) ||
                 (e = hipEventRecord(ev_start[k], s)) != hipSuccess ||
                 (e = (d->use_graph ? hipGraphLaunch(exec, s) : launch(s))) != hipSuccess ||
                 (c == n_chunks - 1 && (n_missing > 0 || d->d_out_valid) &&
@@ -491,17 +555,36 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
                 status = BF_E_DEVICE;
                 break;
             }
+            if (c == n_chunks - 1)
+                issue_ms[i] = std::chrono::duration<double, std::milli>(Clock::now() - avail).count();
             launched.store(L + 1, std::memory_order_release);
         }
     }
+    // on a failure nothing queued may wait for arrivals any longer
+    if (gated && status != BF_OK) __atomic_store_n(&h_gate[1], 1u, __ATOMIC_RELEASE);
     stop.store(true, std::memory_order_release);
     waiter.join();
     const Clock::time_point t_end = Clock::now();
+    if (gated) {
+        recv_stop.store(true, std::memory_order_release);
+        receiver.join();
+    }
     if (status == BF_OK && thread_err.load()) {
         status = BF_E_DEVICE;
         e = hipErrorUnknown;
     }
     if (status != BF_OK) return fail("stream launch");
+    if (gated) {
+        int32_t timed_out = 0;
+        if ((e = hipMemcpyAsync(&timed_out, d_gate_err, sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return fail("gate status");
+        if (timed_out) {
+            e = hipErrorLaunchTimeOut;
+            return fail("device-gated wait for the receiver exceeded gate_timeout_ms");
+        }
+    }
     if ((e = hipEventRecord(ev_sync, s)) != hipSuccess ||
         (e = hipStreamWaitEvent((hipStream_t)stream, ev_sync, 0)) != hipSuccess)
         return fail("stream ordering");
@@ -516,6 +599,10 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     st->ignored_events = sch.ignored + (d->n_events - evi);
     if (d->latency_log_ms && !lat_ms.empty())
         std::memcpy(d->latency_log_ms, lat_ms.data(), sizeof(double) * lat_ms.size());
+    if (d->service_log_ms && !svc_ms.empty())
+        std::memcpy(d->service_log_ms, svc_ms.data(), sizeof(double) * svc_ms.size());
+    if (d->issue_log_ms && !issue_ms.empty())
+        std::memcpy(d->issue_log_ms, issue_ms.data(), sizeof(double) * issue_ms.size());
     // latency and service statistics over the frames after the warm-up
     lat_ms.erase(lat_ms.begin(), lat_ms.begin() + d->warmup_frames);
     svc_ms.erase(svc_ms.begin(), svc_ms.begin() + d->warmup_frames);

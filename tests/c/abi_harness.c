@@ -104,8 +104,20 @@ int main(void)
                 miss += ok[i * 3 + s] == 0;
             }
     CHECK(st.channel_frames == cf && st.missing_frames == miss && miss > 0);
+    d.pacing = BF_STREAM_PACE_GATED;
+    d.gate_timeout_ms = 5;
+    CHECK(beamform_stream_schedule(&d, 1000, 2999, &st) == BF_OK);
+    d.gate_timeout_ms = -1;
+    CHECK(beamform_stream_schedule(&d, 1000, 2999, &st) == BF_E_INVAL);
+    d.gate_timeout_ms = 0;
+    d.pacing = 3;
+    CHECK(beamform_stream_schedule(&d, 1000, 2999, &st) == BF_E_INVAL);
+    d.pacing = BF_STREAM_PACE_HOST;
     d.depth = 0;
     CHECK(beamform_stream_schedule(&d, 1000, 2999, &st) == BF_E_INVAL);
+    /* struct sizes, for the ctypes binding's mirror of these structs */
+    printf("sizes config %zu stream_event %zu stream_desc %zu stream_stats %zu\n", sizeof(bf_config),
+           sizeof(bf_stream_event), sizeof(bf_stream_desc), sizeof(bf_stream_stats));
 
     if (failures) {
         fprintf(stderr, "abi harness: %d failures\n", failures);

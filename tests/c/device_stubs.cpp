@@ -5,6 +5,7 @@
 // reached by that harness.
 #include <hip/hip_runtime.h>
 
+#include "../../paper_1702_04728_amd/csrc/bf_gate.h"
 #include "../../paper_1702_04728_amd/csrc/bf_internal.h"
 #include "../../paper_1702_04728_amd/csrc/bf_trace.h"
 
@@ -14,6 +15,10 @@ hipError_t launch_mfma(const LaunchArgs&, hipStream_t) { return hipErrorNoBinary
 hipError_t launch_fp32_up128(const LaunchArgs&, hipStream_t) { return hipErrorNoBinaryForGpu; }
 hipError_t launch_mfma_up128(const LaunchArgs&, hipStream_t) { return hipErrorNoBinaryForGpu; }
 hipError_t launch_stream_flags(const StreamState*, float*, uint8_t*, int, int, hipStream_t)
+{
+    return hipErrorNoBinaryForGpu;
+}
+hipError_t launch_ingest_gate(const uint32_t*, uint32_t, uint64_t, int32_t*, hipStream_t)
 {
     return hipErrorNoBinaryForGpu;
 }

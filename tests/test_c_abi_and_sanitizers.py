@@ -9,6 +9,7 @@
 * the oracle (oracle/oracle.c) built with AddressSanitizer and
   UndefinedBehaviorSanitizer runs its whole pin suite.
 Every run must end with status 0 and no sanitizer report."""
+import ctypes
 import os
 import shutil
 import subprocess
@@ -51,6 +52,13 @@ def test_c_harness_against_library(tmp_path):
     rc, out = _run([exe])
     print(out)
     assert rc == 0 and out.strip().endswith("abi harness ok"), out
+    # the ctypes binding mirrors the C structs byte for byte
+    sizes = next(l for l in out.splitlines() if l.startswith("sizes ")).split()[1:]
+    c_sizes = dict(zip(sizes[0::2], (int(v) for v in sizes[1::2])))
+    assert c_sizes == {"config": ctypes.sizeof(bf.beamform.BfConfig),
+                       "stream_event": ctypes.sizeof(bf.beamform.BfStreamEvent),
+                       "stream_desc": ctypes.sizeof(bf.beamform.BfStreamDesc),
+                       "stream_stats": ctypes.sizeof(bf.beamform.BfStreamStats)}, c_sizes
 
 
 def test_host_code_under_asan_ubsan(tmp_path):

@@ -1,7 +1,9 @@
 """GPU tests of the serving loop (beamform_stream): per-frame outputs equal the
 batch path bitwise and the oracle within tolerance, across channel churn;
 chunked ingest (partial integrations kept in HBM) equals whole-frame ingest
-bitwise; hipGraph replay equals plain launches bitwise; pacing and admission."""
+bitwise; hipGraph replay equals plain launches bitwise; host-paced and device-gated
+real time (the gate holds every queued launch until its chunk's arrival) and
+admission."""
 import numpy as np
 import pytest
 
@@ -144,6 +146,55 @@ def test_paced_latency(torch_mod, bfm, pool):
     # paced: wall time is at least the stream's own duration
     assert st["wall_s"] >= 300 * budget * 1e-3
     assert st["service_mean_ms"] > 0
+
+
+@pytest.mark.parametrize("chunk", [0, 128])
+def test_gated_pacing_equals_unpaced(torch_mod, bfm, pool, chunk):
+    ring = _ring(torch_mod, pool, 4, 6)
+    _, log_a, a = _stream(torch_mod, bfm, ring, "fp16", chunk=chunk)
+    st, log_b, b = _stream(torch_mod, bfm, ring, "fp16", chunk=chunk, pacing="gated")
+    np.testing.assert_array_equal(log_a, log_b)
+    np.testing.assert_array_equal(a, b)
+    assert st["launches"] == 10 * (384 // (chunk or 384))
+    # held to the receiver's clock: the run lasts at least the stream's own duration
+    assert st["wall_s"] >= 10 * 384 * 2.56e-6
+
+
+@pytest.mark.parametrize("chunk", [0, 128])
+def test_gated_launches_queue_ahead_and_wait_for_data(torch_mod, bfm, pool, chunk):
+    """Device-gated pacing: the host queues launches ahead of their data (issue log
+    negative), yet no frame completes before its last chunk has arrived (latency
+    > 0 for every frame: the gate holds each launch), and the frames keep up."""
+    ring = _ring(torch_mod, pool, 4, 8)
+    ev = [(0, J, c, _f(c)) for c in (10, 200, 400, 600, 800, 1000)]
+    n, warm = 300, 20
+    lat, svc, iss = np.zeros(n), np.zeros(n), np.zeros(n)
+    st, _, _ = _stream(torch_mod, bfm, ring, "fp32", n_frames=n, events=ev, chunk=chunk,
+                       pacing="gated", warmup_frames=warm, latency_log=lat, service_log=svc,
+                       issue_log=iss)
+    print(st)
+    budget = 384 * 2.56e-3
+    assert st["frames"] == n and st["channel_frames"] == 6 * n
+    assert lat.min() > 0.0
+    assert np.median(iss[warm:]) < -budget
+    assert 0 < st["latency_p50_ms"] < budget / 2
+    assert st["late_frames"] <= 3
+    assert np.all(svc[warm:] > 0)
+    assert st["wall_s"] >= n * budget * 1e-3
+
+
+def test_gated_wait_timeout_is_an_error(torch_mod, bfm):
+    """A receiver slower than the gate's bound (9.8 ms frames, 1 ms bound) fails the
+    loop with BF_E_DEVICE; every gate still returns (bounded wait), and the plan
+    serves again afterwards."""
+    ring = torch_mod.zeros((2, 1, 3840, 2048), dtype=torch_mod.uint8, device="cuda")
+    out = torch_mod.zeros((2, 1, 1024, 16), dtype=torch_mod.float32, device="cuda")
+    with bfm.Beamformer([600e6], n_time=3840) as b:
+        with pytest.raises(bfm.BeamformError, match="gate"):
+            b.stream(ring, out, [(0, J, 5, _f(5))], 3, pacing="gated", gate_timeout_ms=1)
+        st, _ = b.stream(ring, out, [(0, J, 5, _f(5))], 2, pacing="gated")
+    torch_mod.cuda.synchronize()
+    assert st["frames"] == 2 and st["channel_frames"] == 2
 
 
 def test_admission_under_memory_cap(torch_mod, bfm, pool):

@@ -125,6 +125,16 @@ def test_schedule_rejects_bad_descriptors():
             bf.stream_schedule([], 5, 4, PSB, 4 * PSB, warmup_frames=bad)
     for ok in (0, 5):
         bf.stream_schedule([], 5, 4, PSB, 4 * PSB, warmup_frames=ok)
+    # pacing: none, host-paced, device-gated; a gated wait's bound is >= 0 (0: default)
+    for ok in ("none", "host", "gated", 0, 1, 2):
+        bf.stream_schedule([], 5, 4, PSB, 4 * PSB, pacing=ok)
+    for bad in (3, -1):
+        with pytest.raises(bf.BeamformError):
+            bf.stream_schedule([], 5, 4, PSB, 4 * PSB, pacing=bad)
+    with pytest.raises(ValueError):
+        bf.stream_schedule([], 5, 4, PSB, 4 * PSB, pacing="fast")
+    with pytest.raises(bf.BeamformError):
+        bf.stream_schedule([], 5, 4, PSB, 4 * PSB, pacing="gated", gate_timeout_ms=-1)
 
 
 def test_join_with_unformable_bin_table_is_ignored():
