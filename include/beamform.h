@@ -244,13 +244,14 @@ typedef struct {
                                  time, host-paced: chunk c of frame i becomes available at
                                  t0 + (i n_time + (c+1) chunk) x 2.56 us and the host
                                  launches it then; 2 real time, device-gated: the same
-                                 availability times, published by a receiver thread as an
-                                 arrival count in pinned host memory; the host queues
-                                 launches ahead of their data (up to BF_STREAM_RUN_AHEAD
-                                 launches not yet completed) and a one-wave kernel in
-                                 front of each holds the stream until its chunk's arrival
-                                 is published, so a host or HIP-runtime stall shorter than
-                                 the queued work delays no frame */
+                                 availability times, kept on the device's constant-rate
+                                 wall clock (aligned to the host clock at start, a gate
+                                 opening at most one probe round trip late, never early):
+                                 the host queues launches ahead of their data (up to
+                                 BF_STREAM_RUN_AHEAD launches not yet completed) and a
+                                 one-wave kernel in front of each holds the stream until
+                                 its chunk's availability, so a host or HIP-runtime stall
+                                 shorter than the queued work delays no frame */
     int32_t use_graph;        /* 1: replay one captured hipGraph per launch; 0: plain launches */
     int64_t mem_cap_bytes;    /* device bytes the stream may use for channel state and its
                                  share of the rings (0: free memory at start); a JOIN that
@@ -286,9 +287,10 @@ typedef struct {
                                  small issue lag means the frame queued behind earlier
                                  ones on the device; negative: queued ahead of its data,
                                  device-gated pacing), filled before returning */
-    int32_t gate_timeout_ms;  /* device-gated pacing: longest wait of one launch for its
-                                 chunk's arrival before the loop fails with BF_E_DEVICE
-                                 (a receiver that stopped); 0 = 1000 ms */
+    int32_t gate_timeout_ms;  /* device-gated pacing: longest wait of one gate for its
+                                 chunk's arrival (a bound on the device-side wait) before
+                                 the loop fails with BF_E_DEVICE; 0 = 1000 ms plus two
+                                 chunk periods */
     int32_t reserved2;        /* must be 0 */
 } bf_stream_desc;
 

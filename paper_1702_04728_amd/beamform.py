@@ -413,7 +413,8 @@ class Beamformer:
         out_ring: CUDA float32 [depth][max_slots][1024][16]; events: (frame, op, channel_id,
         freq_hz) tuples sorted by frame; pacing: False / "none" (as fast as possible),
         True / "host" (host-paced real time) or "gated" (device-gated real time: launches
-        queued ahead of their data, gate_timeout_ms bounding one wait, 0 = 1 s);
+        queued ahead of their data and held on the device clock until it arrives,
+        gate_timeout_ms bounding one wait, 0 = 1 s plus two chunk periods);
         latency and service statistics leave out the first
         warmup_frames frames.  ingest_ok: host uint8 [n_frames][max_slots], 0 where a
         channel-frame did not arrive (its output is zeroed and flagged); out_valid: CUDA

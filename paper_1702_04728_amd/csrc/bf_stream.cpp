@@ -9,13 +9,19 @@
 // A completion thread waits on those events in order and timestamps them;
 // frame latency = completion of the frame's last launch - availability of its
 // last chunk.  Host-paced, the host waits for each chunk's availability before
-// launching it.  Device-gated, a receiver thread publishes the arrival count at
-// the availability times, the host queues launches ahead, and a one-wave gate
-// kernel in front of each launch holds the stream until its chunk has arrived:
-// the HIP runtime's launch calls occasionally block for milliseconds, which a
-// host-paced loop passes on to every frame behind the stall and a queue of
-// gated launches absorbs.  All device state is allocated when the loop starts
-// and freed before it returns.
+// launching it, and latency is taken on the host clock.  Device-gated, the
+// availability times are kept on the device's constant-rate wall clock (the
+// schedule's start aligned once to the host clock): the host queues launches
+// ahead, a one-wave gate kernel in front of each launch holds the stream until
+// the chunk's time, and a one-wave stamp after each frame's last launch gives
+// its completion on the same clock, so latency is the device's own (the data
+// arrive as from a receiver writing into HBM at line rate, whatever the host
+// threads do, and the two clocks' drift does not enter).  The HIP runtime's launch calls now and
+// then block for milliseconds, which a host-paced loop passes on to every frame
+// behind the stall and a queue of gated launches absorbs (a host thread that
+// published arrivals was no better: it could share a CPU with the runtime's
+// busy wait on events and then ran only every few milliseconds).  All device
+// state is allocated when the loop starts and freed before it returns.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,7 +42,9 @@ namespace {
 using Clock = std::chrono::steady_clock;
 constexpr double kSampleS = 2.56e-6;
 constexpr int kInFlight = BF_STREAM_RUN_AHEAD;  // launches the host may run ahead of the device
-constexpr int32_t kGateTimeoutMs = 1000;        // default bound of one gated wait
+constexpr int32_t kGateTimeoutMs = 1000;        // default bound of one gated wait, plus two
+                                                // chunk periods
+constexpr int kClockProbes = 5;                 // host/device clock alignment attempts
 constexpr size_t kTabBytes = bf::kBeamNS * sizeof(int32_t) + bf::kBeamEW * bf::kCyl * sizeof(float2);
 
 // Channel slots, admission and event application (pure host; no device).
@@ -208,6 +216,7 @@ struct LaunchRec {
     int32_t frame;
     bool last_chunk;
     Clock::time_point avail;
+    uint64_t arrival_tick;  // device-gated: availability on the device wall clock
 };
 
 }  // namespace
@@ -299,16 +308,15 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     bf::StreamState* h_state = nullptr;
     unsigned char* h_tab = nullptr;
     const bool gated = d->pacing == BF_STREAM_PACE_GATED;
-    uint32_t* h_gate = nullptr;        // receiver's words (bf_gate.h), coherent pinned memory
-    uint32_t* d_gate = nullptr;        // their device address
-    int32_t* d_gate_err = nullptr;     // set by a gate that timed out
+    uint64_t* d_gate = nullptr;        // [0] low word: set by a gate that timed out; [1] clock probe
+    uint64_t* h_stamp = nullptr;       // [kInFlight] completion stamps, coherent pinned memory
+    uint64_t* d_stamp = nullptr;       // their device address
     hipStream_t s = nullptr;
     hipEvent_t ev_start[kInFlight] = {}, ev_end[kInFlight] = {}, ev_sync = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     auto cleanup = [&]() {
-        if (h_gate) __atomic_store_n(&h_gate[1], 1u, __ATOMIC_RELEASE);  // release queued gates
-        if (s) (void)hipStreamSynchronize(s);
+        if (s) (void)hipStreamSynchronize(s);  // queued gates end by their arrival ticks
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         for (int k = 0; k < kInFlight; ++k) {
@@ -323,8 +331,8 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
         if (d_state) (void)hipFree(d_state);
         if (h_state) (void)hipHostFree(h_state);
         if (h_tab) (void)hipHostFree(h_tab);
-        if (h_gate) (void)hipHostFree(h_gate);
-        if (d_gate_err) (void)hipFree(d_gate_err);
+        if (d_gate) (void)hipFree(d_gate);
+        if (h_stamp) (void)hipHostFree(h_stamp);
     };
     auto fail = [&](const char* what) -> int32_t {
         p->err = std::string(what) + ": " + hipGetErrorString(e);
@@ -342,22 +350,22 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
         (e = hipHostMalloc((void**)&h_tab, kTabBytes * S, 0)) != hipSuccess)
         return fail("hipHostMalloc");
     uint64_t gate_ticks = 0;
+    int khz = 0;
     if (gated) {
-        int khz = 0;
         if ((e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev)) != hipSuccess)
             return fail("wall clock rate");
         if (khz <= 0 || khz > 10000000) {  // a rate in kHz, 10 GHz at most
             e = hipErrorInvalidValue;
             return fail("wall clock rate");
         }
-        gate_ticks = (uint64_t)khz * (uint64_t)(d->gate_timeout_ms ? d->gate_timeout_ms : kGateTimeoutMs);
-        if ((e = hipHostMalloc((void**)&h_gate, sizeof(uint32_t) * bf::kGateWords, hipHostMallocCoherent)) !=
+        const double bound_ms = d->gate_timeout_ms ? (double)d->gate_timeout_ms
+                                                   : kGateTimeoutMs + 2e3 * chunk * kSampleS;
+        gate_ticks = (uint64_t)((double)khz * bound_ms);
+        if ((e = hipMalloc(&d_gate, 2 * sizeof(uint64_t))) != hipSuccess ||
+            (e = hipHostMalloc((void**)&h_stamp, kInFlight * sizeof(uint64_t), hipHostMallocCoherent)) !=
                 hipSuccess ||
-            (e = hipHostGetDevicePointer((void**)&d_gate, h_gate, 0)) != hipSuccess ||
-            (e = hipMalloc(&d_gate_err, sizeof(int32_t))) != hipSuccess)
+            (e = hipHostGetDevicePointer((void**)&d_stamp, h_stamp, 0)) != hipSuccess)
             return fail("gate state");
-        __atomic_store_n(&h_gate[0], 0u, __ATOMIC_RELEASE);
-        __atomic_store_n(&h_gate[1], 0u, __ATOMIC_RELEASE);
     }
     if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return fail("stream");
     for (int k = 0; k < kInFlight; ++k)
@@ -405,13 +413,40 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     // the first paced frame does not pay the first replay's one-time setup.
     {
         std::memset(&h_state[0], 0, bf::kStreamStateHeader);
-        if ((gated && ((e = hipMemsetAsync(d_gate_err, 0, sizeof(int32_t), s)) != hipSuccess ||
-                       (e = bf::launch_ingest_gate(d_gate, 0u, gate_ticks, d_gate_err, s)) != hipSuccess)) ||
+        if ((gated && ((e = hipMemsetAsync(d_gate, 0, 2 * sizeof(uint64_t), s)) != hipSuccess ||
+                       (e = bf::launch_ingest_gate(0, gate_ticks, reinterpret_cast<int32_t*>(d_gate), s)) !=
+                           hipSuccess)) ||
             (e = hipMemcpyAsync(d_state, &h_state[0], bf::kStreamStateHeader, hipMemcpyHostToDevice,
                                 s)) != hipSuccess ||
             (e = (d->use_graph ? hipGraphLaunch(exec, s) : launch(s))) != hipSuccess ||
             (e = hipStreamSynchronize(s)) != hipSuccess)
             return fail("warm-up launch");
+    }
+    // Device-gated: align the device wall clock with the host clock.  Each probe
+    // reads the device clock between two host readings ta < tb; the probe with
+    // the shortest round trip is kept and its reading taken as made at ta, so
+    // that a gate opens at its chunk's availability or at most that round trip
+    // (tens of microseconds) after it, never before.
+    uint64_t clk0 = 0;
+    Clock::time_point clk0_host{};
+    if (gated) {
+        Clock::duration best = Clock::duration::max();
+        for (int k = 0; k < kClockProbes; ++k) {
+            uint64_t v = 0;
+            const Clock::time_point ta = Clock::now();
+            if ((e = bf::launch_wall_clock_probe(d_gate + 1, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return fail("clock probe");
+            const Clock::time_point tb = Clock::now();
+            if ((e = hipMemcpyAsync(&v, d_gate + 1, sizeof v, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return fail("clock probe");
+            if (tb - ta < best) {
+                best = tb - ta;
+                clk0 = v;
+                clk0_host = ta;
+            }
+        }
     }
 
     // ---- completion thread ----
@@ -436,8 +471,12 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
             (void)hipEventElapsedTime(&ms, ev_start[k], ev_end[k]);
             const LaunchRec r = recs[k];
             svc_ms[r.frame] += ms;
-            if (r.last_chunk)
+            if (r.last_chunk && gated) {
+                const uint64_t done = __atomic_load_n(&h_stamp[k], __ATOMIC_ACQUIRE);
+                lat_ms[r.frame] = (double)(int64_t)(done - r.arrival_tick) / (double)khz;
+            } else if (r.last_chunk) {
                 lat_ms[r.frame] = std::chrono::duration<double, std::milli>(now - r.avail).count();
+            }
             completed.store(L + 1, std::memory_order_release);
         }
     });
@@ -463,30 +502,27 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
         return t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(
                         ((double)i * n_time + (double)(c + 1) * chunk) * kSampleS));
     };
+    // the same on the device wall clock (device-gated): t0 mapped through the
+    // probe, the schedule itself in device ticks
+    const double ticks_per_s = (double)khz * 1e3;
+    const double t0_ticks =
+        (double)clk0 +
+        std::max(0.0, std::chrono::duration<double>(t0 - clk0_host).count()) * ticks_per_s;
+    auto arrival_tick = [&](int64_t i, int c) {
+        return (uint64_t)std::ceil(t0_ticks +
+                                   ((double)i * n_time + (double)(c + 1) * chunk) * kSampleS * ticks_per_s);
+    };
     // wait on the host clock until `when` (sleeping while far, yielding near)
-    // or until `quit` is set
-    auto wait_until = [](Clock::time_point when, const std::atomic<bool>* quit) {
+    auto wait_until = [](Clock::time_point when) {
         for (;;) {
             const auto now = Clock::now();
-            if (now >= when || (quit && quit->load(std::memory_order_acquire))) return;
+            if (now >= when) return;
             if (when - now > std::chrono::microseconds(300))
                 std::this_thread::sleep_for(std::chrono::microseconds(100));
             else
                 std::this_thread::yield();
         }
     };
-    // ---- receiver (device-gated pacing): publishes each chunk's arrival ----
-    std::atomic<bool> recv_stop{false};
-    std::thread receiver;
-    if (gated)
-        receiver = std::thread([&]() {
-            const int64_t total = (int64_t)d->n_frames * n_chunks;
-            for (int64_t q = 0; q < total; ++q) {
-                wait_until(avail_at(q / n_chunks, (int)(q % n_chunks)), &recv_stop);
-                if (recv_stop.load(std::memory_order_acquire)) return;
-                __atomic_store_n(&h_gate[0], (uint32_t)(q + 1), __ATOMIC_RELEASE);
-            }
-        });
     int32_t status = BF_OK;
     for (int32_t i = 0; i < d->n_frames && status == BF_OK; ++i) {
         while (evi < d->n_events && d->events[evi].frame <= i) {
@@ -530,7 +566,7 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
         st->min_active = std::min(st->min_active, n_act);
         for (int c = 0; c < n_chunks; ++c, ++L) {
             Clock::time_point avail = avail_at(i, c);
-            if (d->pacing == BF_STREAM_PACE_HOST) wait_until(avail, nullptr);
+            if (d->pacing == BF_STREAM_PACE_HOST) wait_until(avail);
             wait_completed(L - kInFlight + 1);  // slot k of the state/event rings is free
             if (thread_err.load()) { status = BF_E_DEVICE; break; }
             if (d->pacing == BF_STREAM_PACE_NONE) avail = Clock::now();
@@ -541,16 +577,18 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
             hs.n_chunks = n_chunks;
             hs.n_active = n_act;
             std::memcpy(hs.slot, act_launch.data(), sizeof(int32_t) * n_act);
-            recs[k] = LaunchRec{i, c == n_chunks - 1, avail};
+            const uint64_t tick = gated ? arrival_tick(i, c) : 0;
+            recs[k] = LaunchRec{i, c == n_chunks - 1, avail, tick};
             if ((e = hipMemcpyAsync(d_state, &hs, bf::kStreamStateHeader + sizeof(int32_t) * n_act,
                                     hipMemcpyHostToDevice, s)) != hipSuccess ||
-                (gated && (e = bf::launch_ingest_gate(d_gate, (uint32_t)(L + 1), gate_ticks, d_gate_err,
+                (gated && (e = bf::launch_ingest_gate(tick, gate_ticks, reinterpret_cast<int32_t*>(d_gate),
                                                       s)) != hipSuccess) ||
                 (e = hipEventRecord(ev_start[k], s)) != hipSuccess ||
                 (e = (d->use_graph ? hipGraphLaunch(exec, s) : launch(s))) != hipSuccess ||
                 (c == n_chunks - 1 && (n_missing > 0 || d->d_out_valid) &&
                  (e = bf::launch_stream_flags(d_state, d->d_out_ring, d->d_out_valid, S, n_act, s)) !=
                      hipSuccess) ||
+                (gated && c == n_chunks - 1 && (e = bf::launch_wall_clock_probe(d_stamp + k, s)) != hipSuccess) ||
                 (e = hipEventRecord(ev_end[k], s)) != hipSuccess) {
                 status = BF_E_DEVICE;
                 break;
@@ -560,15 +598,9 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
             launched.store(L + 1, std::memory_order_release);
         }
     }
-    // on a failure nothing queued may wait for arrivals any longer
-    if (gated && status != BF_OK) __atomic_store_n(&h_gate[1], 1u, __ATOMIC_RELEASE);
     stop.store(true, std::memory_order_release);
     waiter.join();
     const Clock::time_point t_end = Clock::now();
-    if (gated) {
-        recv_stop.store(true, std::memory_order_release);
-        receiver.join();
-    }
     if (status == BF_OK && thread_err.load()) {
         status = BF_E_DEVICE;
         e = hipErrorUnknown;
@@ -576,13 +608,13 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     if (status != BF_OK) return fail("stream launch");
     if (gated) {
         int32_t timed_out = 0;
-        if ((e = hipMemcpyAsync(&timed_out, d_gate_err, sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
+        if ((e = hipMemcpyAsync(&timed_out, d_gate, sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
                 hipSuccess ||
             (e = hipStreamSynchronize(s)) != hipSuccess)
             return fail("gate status");
         if (timed_out) {
             e = hipErrorLaunchTimeOut;
-            return fail("device-gated wait for the receiver exceeded gate_timeout_ms");
+            return fail("a device-gated wait for a chunk's arrival exceeded gate_timeout_ms");
         }
     }
     if ((e = hipEventRecord(ev_sync, s)) != hipSuccess ||

@@ -2,7 +2,8 @@
 // frame's last launch, the output entry of every active slot whose frame did
 // not arrive is zeroed, and every active entry's valid flag is written (kept
 // out of the beamforming kernels, which only skip a missing slot).  Device-
-// gated pacing: a one-wave wait on the receiver's arrival count.
+// gated pacing: a one-wave wait for a chunk's arrival time on the device's
+// wall clock.
 #include <hip/hip_runtime.h>
 
 #include "bf_gate.h"
@@ -29,19 +30,17 @@ __global__ __launch_bounds__(kFlagThreads) void bf_stream_flags_kernel(const Str
     }
 }
 
-// One lane polls the receiver's words with system-scope loads (they bypass
-// the GPU caches, so the host's stores are seen), sleeping between polls; the
-// device wall clock bounds the wait.
-__global__ __launch_bounds__(64) void bf_ingest_gate_kernel(const uint32_t* gate, uint32_t target,
-                                                            uint64_t max_ticks, int32_t* timed_out)
+// One lane reads the device wall clock, sleeping between reads, until the
+// chunk's arrival tick; the wait is bounded by max_ticks from its start.
+__global__ __launch_bounds__(64) void bf_ingest_gate_kernel(uint64_t arrival_tick, uint64_t max_ticks,
+                                                            int32_t* timed_out)
 {
     if (threadIdx.x != 0) return;
     const uint64_t t0 = wall_clock64();
     for (;;) {
-        const uint32_t open = __hip_atomic_load(gate + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        const uint32_t have = __hip_atomic_load(gate, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-        if (open != 0 || (int32_t)(have - target) >= 0) return;
-        if (wall_clock64() - t0 > max_ticks) {
+        const uint64_t now = wall_clock64();
+        if (now >= arrival_tick) return;
+        if (now - t0 > max_ticks) {
             *timed_out = 1;
             return;
         }
@@ -49,13 +48,26 @@ __global__ __launch_bounds__(64) void bf_ingest_gate_kernel(const uint32_t* gate
     }
 }
 
+// System-scope release store: visible to the host (out may be pinned host
+// memory) once the kernel's completion has been observed.
+__global__ __launch_bounds__(64) void bf_wall_clock_probe_kernel(uint64_t* out)
+{
+    if (threadIdx.x == 0) __hip_atomic_store(out, wall_clock64(), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 }  // namespace
 
-hipError_t launch_ingest_gate(const uint32_t* gate, uint32_t target, uint64_t max_ticks,
-                              int32_t* timed_out, hipStream_t stream)
+hipError_t launch_ingest_gate(uint64_t arrival_tick, uint64_t max_ticks, int32_t* timed_out,
+                              hipStream_t stream)
 {
-    hipLaunchKernelGGL(bf_ingest_gate_kernel, dim3(1), dim3(64), 0, stream, gate, target, max_ticks,
+    hipLaunchKernelGGL(bf_ingest_gate_kernel, dim3(1), dim3(64), 0, stream, arrival_tick, max_ticks,
                        timed_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_clock_probe(uint64_t* out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(bf_wall_clock_probe_kernel, dim3(1), dim3(64), 0, stream, out);
     return hipGetLastError();
 }
 

@@ -156,7 +156,7 @@ def test_gated_pacing_equals_unpaced(torch_mod, bfm, pool, chunk):
     np.testing.assert_array_equal(log_a, log_b)
     np.testing.assert_array_equal(a, b)
     assert st["launches"] == 10 * (384 // (chunk or 384))
-    # held to the receiver's clock: the run lasts at least the stream's own duration
+    # held to the arrival clock: the run lasts at least the stream's own duration
     assert st["wall_s"] >= 10 * 384 * 2.56e-6
 
 
@@ -164,7 +164,9 @@ def test_gated_pacing_equals_unpaced(torch_mod, bfm, pool, chunk):
 def test_gated_launches_queue_ahead_and_wait_for_data(torch_mod, bfm, pool, chunk):
     """Device-gated pacing: the host queues launches ahead of their data (issue log
     negative), yet no frame completes before its last chunk has arrived (latency
-    > 0 for every frame: the gate holds each launch), and the frames keep up."""
+    > 0 for every frame: the gate holds each launch until its arrival time on the
+    device clock), a gate opens close to that time (median latency within 0.15 ms
+    of the device time), and the frames keep up."""
     ring = _ring(torch_mod, pool, 4, 8)
     ev = [(0, J, c, _f(c)) for c in (10, 200, 400, 600, 800, 1000)]
     n, warm = 300, 20
@@ -177,16 +179,16 @@ def test_gated_launches_queue_ahead_and_wait_for_data(torch_mod, bfm, pool, chun
     assert st["frames"] == n and st["channel_frames"] == 6 * n
     assert lat.min() > 0.0
     assert np.median(iss[warm:]) < -budget
-    assert 0 < st["latency_p50_ms"] < budget / 2
+    assert 0 < st["latency_p50_ms"] < st["service_mean_ms"] + 0.15
     assert st["late_frames"] <= 3
     assert np.all(svc[warm:] > 0)
     assert st["wall_s"] >= n * budget * 1e-3
 
 
 def test_gated_wait_timeout_is_an_error(torch_mod, bfm):
-    """A receiver slower than the gate's bound (9.8 ms frames, 1 ms bound) fails the
-    loop with BF_E_DEVICE; every gate still returns (bounded wait), and the plan
-    serves again afterwards."""
+    """A gate that would wait longer than its bound (9.8 ms frames queued ahead of
+    their data, 1 ms bound) fails the loop with BF_E_DEVICE; every gate still
+    returns (bounded wait), and the plan serves again afterwards."""
     ring = torch_mod.zeros((2, 1, 3840, 2048), dtype=torch_mod.uint8, device="cuda")
     out = torch_mod.zeros((2, 1, 1024, 16), dtype=torch_mod.float32, device="cuda")
     with bfm.Beamformer([600e6], n_time=3840) as b:
