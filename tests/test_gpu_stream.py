@@ -237,7 +237,8 @@ def test_stream_argument_errors(torch_mod, bfm, pool):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16", "fp32_mfma"])
 @pytest.mark.parametrize("chunk", [0, 128])
-def test_lossy_ingest_zeroes_and_flags_missing_frames(torch_mod, bfm, pool, precision, chunk):
+@pytest.mark.parametrize("pacing", ["none", "gated"])
+def test_lossy_ingest_zeroes_and_flags_missing_frames(torch_mod, bfm, pool, precision, chunk, pacing):
     """Channel-frames the ingest did not deliver (ingest_ok = 0: an empty or late
     ring entry) are skipped: their output entry is exactly zero and flagged 0 in
     out_valid, and they are counted; every delivered one is flagged 1 and equals
@@ -249,7 +250,7 @@ def test_lossy_ingest_zeroes_and_flags_missing_frames(torch_mod, bfm, pool, prec
     depth, slots = 4, 6
     valid = torch_mod.full((depth, slots), 255, dtype=torch_mod.uint8, device="cuda")
     st, log, out = _stream(torch_mod, bfm, ring, precision, chunk=chunk, ingest_ok=ok,
-                           out_valid=valid)
+                           out_valid=valid, pacing=pacing)
     valid = valid.cpu().numpy()
     assert st["missing_frames"] == int(((log >= 0) & (ok == 0)).sum()) > 0
     ring_np = ring.cpu().numpy()
