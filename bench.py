@@ -252,13 +252,15 @@ def time_path(torch, bf, prec, raw, freqs, units, args, sin_phi=None, u8=None, u
     }
 
 
-def serve(torch, bf, synth, prec, n_frames: int, to_clamps: bool = False, pacing="gated"):
+def serve(torch, bf, synth, prec, n_frames: int, to_clamps: bool = False, pacing="gated",
+          chunk: int = 0):
     """Serving loop (config 3): seeded churn of 16-128 channels from 1024 ids, 0.983 ms
     frames paced in real time, hipGraph replay; input ring of 8 frames x 128 slots
     (805 MB, larger than the 256 MB Infinity Cache) tiled from 16 seeded frames.
     to_clamps: start at 120 channels and drift up, down and up again so that the run
     spends frames at both the 128- and the 16-channel clamp (latency reported per
-    active count at the two ends)."""
+    active count at the two ends).  chunk: samples per launch (0: whole frames; 128: three
+    launches per frame, partial sums in HBM, latency from the last chunk's arrival)."""
     depth, slots = 8, 128
     if to_clamps:
         rj, rl = synth.churn_rates_to_clamps(n_frames)
@@ -274,13 +276,14 @@ def serve(torch, bf, synth, prec, n_frames: int, to_clamps: bool = False, pacing
     del pool
     lat = np.zeros(n_frames)
     with bf.Beamformer([600e6], precision=prec) as b:
-        st, slot_log = b.stream(ring, out, events, n_frames, pacing=pacing, use_graph=True,
-                                log_slots=True, latency_log=lat)
+        st, slot_log = b.stream(ring, out, events, n_frames, chunk=chunk, pacing=pacing,
+                                use_graph=True, log_slots=True, latency_log=lat)
     torch.cuda.synchronize()
     del ring, out
     n_act = (slot_log >= 0).sum(axis=1)
-    log("%s serving%s: p50 %.3f ms p99 %.3f ms max %.3f ms late %d/%d" % (
-        prec, " to clamps" if to_clamps else "", st["latency_p50_ms"], st["latency_p99_ms"],
+    log("%s serving%s%s: p50 %.3f ms p99 %.3f ms max %.3f ms late %d/%d" % (
+        prec, " to clamps" if to_clamps else "", " chunk %d" % chunk if chunk else "",
+        st["latency_p50_ms"], st["latency_p99_ms"],
         st["latency_max_ms"], st["late_frames"], st["frames"]))
     by_active = {}
     for k in (int(n_act.max()), int(n_act.min())):
@@ -289,6 +292,7 @@ def serve(torch, bf, synth, prec, n_frames: int, to_clamps: bool = False, pacing
                              "latency_p50_ms": round(float(np.percentile(sel, 50)), 4),
                              "latency_p99_ms": round(float(np.percentile(sel, 99)), 4)}
     return {"frames": st["frames"], "budget_ms": 0.98304, "pacing": pacing,
+            "chunk_samples": chunk or 384,
             "latency_by_active_channels": by_active,
             "latency_p50_ms": round(st["latency_p50_ms"], 4),
             "latency_p99_ms": round(st["latency_p99_ms"], 4),
@@ -505,6 +509,8 @@ def main():
                                              pacing=args.pacing)
             results[prec]["serving_to_clamps"] = serve(torch, bf, synth, prec, args.serve_frames,
                                                        to_clamps=True, pacing=args.pacing)
+            results[prec]["serving_chunk128"] = serve(torch, bf, synth, prec, args.serve_frames,
+                                                      pacing=args.pacing, chunk=128)
 
     if not args.no_sweep:
         n_list = [int(v) for v in args.sweep_list.split(",")]
