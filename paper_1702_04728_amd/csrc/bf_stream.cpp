@@ -495,8 +495,11 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     int32_t evi = 0;
     int64_t L = 0;
     st->min_active = d->n_frames > 0 ? S : 0;
-    const Clock::time_point t_start = Clock::now();
-    const Clock::time_point t0 = t_start + std::chrono::microseconds(500);
+    // The schedule starts once frame 0's events (the initial channel set) have
+    // been applied: t0 = that moment + 0.5 ms, so that their table uploads do not
+    // count against the first frame.
+    Clock::time_point t_start = Clock::now();
+    Clock::time_point t0 = t_start + std::chrono::microseconds(500);
     // availability of chunk c of frame i (the last sample's arrival)
     auto avail_at = [&](int64_t i, int c) {
         return t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(
@@ -505,9 +508,14 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     // the same on the device wall clock (device-gated): t0 mapped through the
     // probe, the schedule itself in device ticks
     const double ticks_per_s = (double)khz * 1e3;
-    const double t0_ticks =
-        (double)clk0 +
-        std::max(0.0, std::chrono::duration<double>(t0 - clk0_host).count()) * ticks_per_s;
+    double t0_ticks = 0.0;
+    auto start_schedule = [&]() {
+        t_start = Clock::now();
+        t0 = t_start + std::chrono::microseconds(500);
+        t0_ticks = (double)clk0 +
+                   std::max(0.0, std::chrono::duration<double>(t0 - clk0_host).count()) * ticks_per_s;
+    };
+    start_schedule();
     auto arrival_tick = [&](int64_t i, int c) {
         return (uint64_t)std::ceil(t0_ticks +
                                    ((double)i * n_time + (double)(c + 1) * chunk) * kSampleS * ticks_per_s);
@@ -556,6 +564,7 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
             tab_launch[slot] = L;
         }
         if (status != BF_OK) break;
+        if (i == 0) start_schedule();
         const int n_act = sch.active(act.data());
         if (d->slot_log)
             std::memcpy(d->slot_log + (size_t)i * S, sch.slot_chan.data(), sizeof(int32_t) * S);
