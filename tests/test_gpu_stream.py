@@ -148,11 +148,12 @@ def test_paced_latency(torch_mod, bfm, pool):
     assert st["service_mean_ms"] > 0
 
 
-@pytest.mark.parametrize("chunk", [0, 128])
-def test_gated_pacing_equals_unpaced(torch_mod, bfm, pool, chunk):
+@pytest.mark.parametrize("chunk,use_graph", [(0, True), (128, True), (0, False)])
+def test_gated_pacing_equals_unpaced(torch_mod, bfm, pool, chunk, use_graph):
     ring = _ring(torch_mod, pool, 4, 6)
     _, log_a, a = _stream(torch_mod, bfm, ring, "fp16", chunk=chunk)
-    st, log_b, b = _stream(torch_mod, bfm, ring, "fp16", chunk=chunk, pacing="gated")
+    st, log_b, b = _stream(torch_mod, bfm, ring, "fp16", chunk=chunk, pacing="gated",
+                           use_graph=use_graph)
     np.testing.assert_array_equal(log_a, log_b)
     np.testing.assert_array_equal(a, b)
     assert st["launches"] == 10 * (384 // (chunk or 384))
