@@ -11,10 +11,18 @@
 
 namespace bf {
 
+// Launch state words one lane of the gate copies, at most (64 lanes cover a
+// StreamState of BF_STREAM_MAX_SLOTS slots plus its header).
+constexpr int kGateStateWordsPerLane = 17;
+
 // Enqueue on `stream` a wait until the device wall clock (wall_clock64())
-// reaches arrival_tick.  The wait is bounded: after max_ticks the kernel sets
-// *timed_out = 1 and returns.
+// reaches arrival_tick.  Before waiting, the kernel copies state_words 32-bit
+// words of the launch's state from state_src (pinned host memory, read with
+// system-scope loads) to state_dst (device memory, at most
+// 64 x kGateStateWordsPerLane words), so that the launch needs no copy of its own.  The wait is bounded: after
+// max_ticks the kernel sets *timed_out = 1 and returns.
 hipError_t launch_ingest_gate(uint64_t arrival_tick, uint64_t max_ticks, int32_t* timed_out,
+                              const uint32_t* state_src, uint32_t* state_dst, uint32_t state_words,
                               hipStream_t stream);
 
 // Enqueue on `stream` one read of the device wall clock into *out (device or

@@ -305,7 +305,8 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     float2* d_ew = nullptr;
     float* d_partial = nullptr;
     bf::StreamState* d_state = nullptr;
-    bf::StreamState* h_state = nullptr;
+    bf::StreamState* h_state = nullptr;  // [kInFlight] launch states, coherent pinned memory
+    bf::StreamState* d_hstate = nullptr; // their device address (the gates read them)
     unsigned char* h_tab = nullptr;
     const bool gated = d->pacing == BF_STREAM_PACE_GATED;
     uint64_t* d_gate = nullptr;        // [0] low word: set by a gate that timed out; [1] clock probe
@@ -346,7 +347,9 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     if (n_chunks > 1 &&
         (e = hipMalloc(&d_partial, (size_t)S * 4 * bf::kPartialPerWg * sizeof(float))) != hipSuccess)
         return fail("hipMalloc partial sums");
-    if ((e = hipHostMalloc((void**)&h_state, sizeof(bf::StreamState) * kInFlight, 0)) != hipSuccess ||
+    if ((e = hipHostMalloc((void**)&h_state, sizeof(bf::StreamState) * kInFlight, hipHostMallocCoherent)) !=
+            hipSuccess ||
+        (e = hipHostGetDevicePointer((void**)&d_hstate, h_state, 0)) != hipSuccess ||
         (e = hipHostMalloc((void**)&h_tab, kTabBytes * S, 0)) != hipSuccess)
         return fail("hipHostMalloc");
     uint64_t gate_ticks = 0;
@@ -414,8 +417,8 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
     {
         std::memset(&h_state[0], 0, bf::kStreamStateHeader);
         if ((gated && ((e = hipMemsetAsync(d_gate, 0, 2 * sizeof(uint64_t), s)) != hipSuccess ||
-                       (e = bf::launch_ingest_gate(0, gate_ticks, reinterpret_cast<int32_t*>(d_gate), s)) !=
-                           hipSuccess)) ||
+                       (e = bf::launch_ingest_gate(0, gate_ticks, reinterpret_cast<int32_t*>(d_gate), nullptr,
+                                                   nullptr, 0, s)) != hipSuccess)) ||
             (e = hipMemcpyAsync(d_state, &h_state[0], bf::kStreamStateHeader, hipMemcpyHostToDevice,
                                 s)) != hipSuccess ||
             (e = (d->use_graph ? hipGraphLaunch(exec, s) : launch(s))) != hipSuccess ||
@@ -588,10 +591,15 @@ int32_t beamform_stream(bf_plan* p, const bf_stream_desc* d, bf_stream_stats* st
             std::memcpy(hs.slot, act_launch.data(), sizeof(int32_t) * n_act);
             const uint64_t tick = gated ? arrival_tick(i, c) : 0;
             recs[k] = LaunchRec{i, c == n_chunks - 1, avail, tick};
-            if ((e = hipMemcpyAsync(d_state, &hs, bf::kStreamStateHeader + sizeof(int32_t) * n_act,
-                                    hipMemcpyHostToDevice, s)) != hipSuccess ||
+            // the state goes to the device by a copy, or (device-gated) inside the
+            // gate kernel, which reads it from the pinned ring entry
+            const size_t state_bytes = bf::kStreamStateHeader + sizeof(int32_t) * n_act;
+            if ((!gated && (e = hipMemcpyAsync(d_state, &hs, state_bytes, hipMemcpyHostToDevice, s)) !=
+                               hipSuccess) ||
                 (gated && (e = bf::launch_ingest_gate(tick, gate_ticks, reinterpret_cast<int32_t*>(d_gate),
-                                                      s)) != hipSuccess) ||
+                                                      reinterpret_cast<const uint32_t*>(d_hstate + k),
+                                                      reinterpret_cast<uint32_t*>(d_state),
+                                                      (uint32_t)(state_bytes / 4), s)) != hipSuccess) ||
                 (e = hipEventRecord(ev_start[k], s)) != hipSuccess ||
                 (e = (d->use_graph ? hipGraphLaunch(exec, s) : launch(s))) != hipSuccess ||
                 (c == n_chunks - 1 && (n_missing > 0 || d->d_out_valid) &&

@@ -12,6 +12,8 @@
 namespace bf {
 namespace {
 
+static_assert(sizeof(StreamState) <= 4 * 64 * kGateStateWordsPerLane, "gate copies the whole state");
+
 constexpr int kFlagThreads = 256;
 
 __global__ __launch_bounds__(kFlagThreads) void bf_stream_flags_kernel(const StreamState* st, float* out,
@@ -30,11 +32,27 @@ __global__ __launch_bounds__(kFlagThreads) void bf_stream_flags_kernel(const Str
     }
 }
 
-// One lane reads the device wall clock, sleeping between reads, until the
-// chunk's arrival tick; the wait is bounded by max_ticks from its start.
+// The wave copies the launch's state into place, then one lane reads the
+// device wall clock, sleeping between reads, until the chunk's arrival tick;
+// the wait is bounded by max_ticks from its start.
 __global__ __launch_bounds__(64) void bf_ingest_gate_kernel(uint64_t arrival_tick, uint64_t max_ticks,
-                                                            int32_t* timed_out)
+                                                            int32_t* timed_out, const uint32_t* state_src,
+                                                            uint32_t* state_dst, uint32_t state_words)
 {
+    // Branch-free so that all of a lane's loads are issued before one wait (one
+    // host round trip) and the stores follow without waits: indices past the
+    // end are clamped to the last word, which such lanes load and store again
+    // with its own value.
+    if (state_words > 0) {
+        const uint32_t last = state_words - 1;
+        uint32_t v[kGateStateWordsPerLane];
+#pragma unroll
+        for (int j = 0; j < kGateStateWordsPerLane; ++j)
+            v[j] = __hip_atomic_load(state_src + min(threadIdx.x + 64u * j, last), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_SYSTEM);
+#pragma unroll
+        for (int j = 0; j < kGateStateWordsPerLane; ++j) state_dst[min(threadIdx.x + 64u * j, last)] = v[j];
+    }
     if (threadIdx.x != 0) return;
     const uint64_t t0 = wall_clock64();
     for (;;) {
@@ -58,10 +76,12 @@ __global__ __launch_bounds__(64) void bf_wall_clock_probe_kernel(uint64_t* out)
 }  // namespace
 
 hipError_t launch_ingest_gate(uint64_t arrival_tick, uint64_t max_ticks, int32_t* timed_out,
+                              const uint32_t* state_src, uint32_t* state_dst, uint32_t state_words,
                               hipStream_t stream)
 {
+    if (state_words > 64 * kGateStateWordsPerLane) return hipErrorInvalidValue;
     hipLaunchKernelGGL(bf_ingest_gate_kernel, dim3(1), dim3(64), 0, stream, arrival_tick, max_ticks,
-                       timed_out);
+                       timed_out, state_src, state_dst, state_words);
     return hipGetLastError();
 }
 

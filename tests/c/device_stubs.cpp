@@ -18,7 +18,10 @@ hipError_t launch_stream_flags(const StreamState*, float*, uint8_t*, int, int, h
 {
     return hipErrorNoBinaryForGpu;
 }
-hipError_t launch_ingest_gate(uint64_t, uint64_t, int32_t*, hipStream_t) { return hipErrorNoBinaryForGpu; }
+hipError_t launch_ingest_gate(uint64_t, uint64_t, int32_t*, const uint32_t*, uint32_t*, uint32_t, hipStream_t)
+{
+    return hipErrorNoBinaryForGpu;
+}
 hipError_t launch_wall_clock_probe(uint64_t*, hipStream_t) { return hipErrorNoBinaryForGpu; }
 void trace_push(const char*) {}
 void trace_pop() {}
