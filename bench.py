@@ -281,10 +281,12 @@ def serve(torch, bf, synth, prec, n_frames: int, to_clamps: bool = False, pacing
     torch.cuda.synchronize()
     del ring, out
     n_act = (slot_log >= 0).sum(axis=1)
-    log("%s serving%s%s: p50 %.3f ms p99 %.3f ms max %.3f ms late %d/%d" % (
+    late_idx = [int(i) for i in np.nonzero(lat > 0.98304)[0][:10]]
+    log("%s serving%s%s: p50 %.3f ms p99 %.3f ms max %.3f ms late %d/%d%s" % (
         prec, " to clamps" if to_clamps else "", " chunk %d" % chunk if chunk else "",
         st["latency_p50_ms"], st["latency_p99_ms"],
-        st["latency_max_ms"], st["late_frames"], st["frames"]))
+        st["latency_max_ms"], st["late_frames"], st["frames"],
+        " (frames %s)" % late_idx if late_idx else ""))
     by_active = {}
     for k in (int(n_act.max()), int(n_act.min())):
         sel = lat[n_act == k]
@@ -298,12 +300,28 @@ def serve(torch, bf, synth, prec, n_frames: int, to_clamps: bool = False, pacing
             "latency_p99_ms": round(st["latency_p99_ms"], 4),
             "latency_max_ms": round(st["latency_max_ms"], 4),
             "late_frames": st["late_frames"],
+            "late_frame_indices": late_idx,
             "service_mean_ms": round(st["service_mean_ms"], 4),
             "service_p99_ms": round(st["service_p99_ms"], 4),
             "active_channels": [st["min_active"], st["max_active"]],
             "joins": st["joins"], "leaves": st["leaves"],
             "rejected_joins": st["rejected_joins"], "clamped_events": clamped,
             "channel_frames": st["channel_frames"], "wall_s": round(st["wall_s"], 3)}
+
+
+def gated_pacing_works(torch, bf, synth):
+    """A two-frame device-gated run of one channel; on failure (the device wall clock
+    not available, say) returns the library's message, else None."""
+    ring = torch.zeros((2, 1, 384, 2048), dtype=torch.uint8, device="cuda")
+    out = torch.empty((2, 1, 1024, 16), dtype=torch.float32, device="cuda")
+    try:
+        with bf.Beamformer([600e6], precision="fp32") as b:
+            b.stream(ring, out, [(0, 1, 5, float(synth.chan_freq_hz(5)))], 2, pacing="gated",
+                     log_slots=False)
+        torch.cuda.synchronize()
+    except bf.BeamformError as exc:
+        return str(exc)
+    return None
 
 
 def sweep_point(torch, bf, synth, pool, prec, n, n_frames, chunk, warmup, pacing):
@@ -503,6 +521,14 @@ def main():
             entry["hbm"]["copy_GBs"] = round(copy_gbs, 1)
             entry["hbm"]["frac_of_copy"] = round(entry["hbm"]["achieved_GBs"] / copy_gbs, 4)
 
+    pacing_note = None
+    if args.pacing == "gated" and (args.serve_frames > 0 or not args.no_sweep):
+        err = gated_pacing_works(torch, bf, synth)
+        if err:
+            log("device-gated pacing failed (%s): the serving loop and sweep run host-paced" % err)
+            args.pacing = "host"
+            pacing_note = "device-gated pacing failed (%s); host-paced instead" % err
+
     if args.serve_frames > 0:
         for prec in paths:
             results[prec]["serving"] = serve(torch, bf, synth, prec, args.serve_frames,
@@ -546,6 +572,7 @@ def main():
         "p99_frame_latency_ms": head.get("serving", {}).get("latency_p99_ms"),
         "sustained": {PATH_NAME[p]: sustained_summary(results[p].get("sweep"))
                       for p in paths if "sweep" in results[p]},
+        "pacing": args.pacing if pacing_note is None else pacing_note,
         "paths": {PATH_NAME[p]: results[p] for p in paths},
     }
     if not args.no_cpu_baseline:

@@ -220,7 +220,8 @@ int32_t beamform_frame_tracking_noalloc(bf_plan *plan, const uint8_t *d_in, int3
 #define BF_STREAM_PACE_NONE 0
 #define BF_STREAM_PACE_HOST 1
 #define BF_STREAM_PACE_GATED 2
-#define BF_STREAM_RUN_AHEAD 16 /* launches queued and not yet completed, at most */
+#define BF_STREAM_RUN_AHEAD 48 /* launches queued and not yet completed, at most (16 frames
+                                  of 128-sample chunks) */
 
 typedef struct {
     int32_t frame;       /* applied before frame `frame` is processed */
